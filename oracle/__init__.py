@@ -1,0 +1,190 @@
+"""CPU oracle for sliding window sums and minimizer seed tables.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline leg may import this package; the library and its product path never
+do.  It shares no code with the HIP implementation.
+
+``oracle.c`` holds the arithmetic (plain C loops, each routine citing the
+passage of Snytsar & Turakhia, arXiv:1811.10074, that it writes out).  This
+module only marshals numpy arrays into it.  ``brute.py`` is a second, tiny,
+pure-Python formulation used to check ``oracle.c`` on small inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OPS = {"add": 0, "min": 1, "max": 2, "affine": 3}
+FORWARD = 1   # forward k-mer instead of canonical
+IDENTITY = 2  # k-mer value instead of its hash
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(out: str = LIB_PATH, src: str = _SRC, extra_flags=()) -> str:
+    """Compile oracle.c with gcc into a shared library (always recompiles)."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+           *extra_flags, "-o", tmp, src]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def _bind(lib):
+    u64, u32p, u64p, u8p = (ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32),
+                            ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint8))
+    ll = ctypes.c_longlong
+    lib.oracle_sliding_sum.argtypes = [ctypes.c_int, u64, u32p, u64, u32p]
+    lib.oracle_sliding_sum.restype = ll
+    lib.oracle_mix64.argtypes = [u64]
+    lib.oracle_mix64.restype = u64
+    lib.oracle_mix64_inv.argtypes = [u64]
+    lib.oracle_mix64_inv.restype = u64
+    lib.oracle_mix64_array.argtypes = [u64p, u64, ctypes.c_int, u64p]
+    lib.oracle_mix64_array.restype = None
+    lib.oracle_base_code.argtypes = [ctypes.c_uint8]
+    lib.oracle_base_code.restype = ctypes.c_int
+    lib.oracle_kmers.argtypes = [u8p, u64, ctypes.c_uint32, ctypes.c_uint32, u64p]
+    lib.oracle_kmers.restype = ll
+    for name in ("oracle_minimizers_naive", "oracle_minimizers_deque"):
+        f = getattr(lib, name)
+        f.argtypes = [u8p, u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                      u64p, u32p, u64]
+        f.restype = ll
+    lib.oracle_minimizers_batch.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_uint32, ctypes.c_uint32, u64p, u32p,
+                                            u32p, u64, u64p]
+    lib.oracle_minimizers_batch.restype = ll
+    return lib
+
+
+def load(path: str | None = None):
+    """Load liboracle.so (building it first only when it does not exist).
+
+    With ``path`` given, load that library (e.g. a deliberately mutated build)
+    without caching it."""
+    global _lib
+    if path is not None:
+        return _bind(ctypes.CDLL(path))
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                build()
+            _lib = _bind(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _as_bytes(seq) -> np.ndarray:
+    if isinstance(seq, (bytes, bytearray)):
+        return np.frombuffer(bytes(seq), dtype=np.uint8)
+    if isinstance(seq, str):
+        return np.frombuffer(seq.encode("ascii"), dtype=np.uint8)
+    return np.ascontiguousarray(seq, dtype=np.uint8)
+
+
+def sliding_sum(op: str, w: int, x: np.ndarray, lib=None) -> np.ndarray:
+    """Eq. 2 as a left fold.  x: uint32[n] (uint32[n, 2] of (a, b) for affine)."""
+    lib = lib or load()
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    pair = op == "affine"
+    n = x.shape[0]
+    if pair and (x.ndim != 2 or x.shape[1] != 2):
+        raise ValueError("affine input must be uint32[n, 2]")
+    cnt = max(0, n - w + 1) if w >= 1 else 0
+    y = np.zeros((cnt, 2) if pair else (cnt,), dtype=np.uint32)
+    r = lib.oracle_sliding_sum(OPS[op], w, _ptr(x, ctypes.c_uint32), n,
+                               _ptr(y, ctypes.c_uint32))
+    if r < 0:
+        raise ValueError("oracle_sliding_sum rejected op=%s w=%d" % (op, w))
+    assert r == cnt
+    return y
+
+
+def mix64(x, inverse: bool = False, lib=None):
+    lib = lib or load()
+    if np.isscalar(x):
+        return int((lib.oracle_mix64_inv if inverse else lib.oracle_mix64)(int(x)))
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    y = np.empty_like(x)
+    lib.oracle_mix64_array(_ptr(x, ctypes.c_uint64), x.size, int(inverse),
+                           _ptr(y, ctypes.c_uint64))
+    return y
+
+
+def flags_of(canonical: bool = True, hashed: bool = True) -> int:
+    return (0 if canonical else FORWARD) | (0 if hashed else IDENTITY)
+
+
+def kmers(seq, k: int, canonical: bool = True, hashed: bool = True, lib=None) -> np.ndarray:
+    lib = lib or load()
+    s = _as_bytes(seq)
+    n = s.size
+    out = np.zeros(max(0, n - k + 1), dtype=np.uint64)
+    r = lib.oracle_kmers(_ptr(s, ctypes.c_uint8), n, k, flags_of(canonical, hashed),
+                         _ptr(out, ctypes.c_uint64))
+    if r < 0:
+        raise ValueError("oracle_kmers rejected k=%d" % k)
+    return out
+
+
+def window_bound(n: int, k: int, w: int) -> int:
+    """Number of windows of w k-mers in a sequence of n bases."""
+    return max(0, n - k - w + 2)
+
+
+def minimizers(seq, k: int, w: int, canonical: bool = True, hashed: bool = True,
+               method: str = "deque", lib=None):
+    """Deduplicated (hash uint64, pos uint32) minimizers of one sequence."""
+    lib = lib or load()
+    s = _as_bytes(seq)
+    n = s.size
+    cap = window_bound(n, k, w)
+    h = np.zeros(max(cap, 1), dtype=np.uint64)
+    p = np.zeros(max(cap, 1), dtype=np.uint32)
+    f = lib.oracle_minimizers_naive if method == "naive" else lib.oracle_minimizers_deque
+    r = f(_ptr(s, ctypes.c_uint8), n, k, w, flags_of(canonical, hashed),
+          _ptr(h, ctypes.c_uint64), _ptr(p, ctypes.c_uint32), cap)
+    if r < 0:
+        raise ValueError("oracle minimizers rejected k=%d w=%d" % (k, w))
+    assert r <= cap
+    return h[:r].copy(), p[:r].copy()
+
+
+def minimizers_batch(seqs: np.ndarray, offsets: np.ndarray, k: int, w: int,
+                     canonical: bool = True, hashed: bool = True, lib=None):
+    """Per-read minimizers of reads seqs[offsets[r]:offsets[r+1]].
+
+    Returns (hash, pos, read, read_offsets) with read-major order, pos relative
+    to the read start, read_offsets of length nreads + 1."""
+    lib = lib or load()
+    s = _as_bytes(seqs)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nreads = off.size - 1
+    lens = np.diff(off.astype(np.int64))
+    cap = int(np.maximum(lens - k - w + 2, 0).sum())
+    h = np.zeros(max(cap, 1), dtype=np.uint64)
+    p = np.zeros(max(cap, 1), dtype=np.uint32)
+    rd = np.zeros(max(cap, 1), dtype=np.uint32)
+    ro = np.zeros(nreads + 1, dtype=np.uint64)
+    r = lib.oracle_minimizers_batch(_ptr(s, ctypes.c_uint8), _ptr(off, ctypes.c_uint64),
+                                    nreads, k, w, flags_of(canonical, hashed),
+                                    _ptr(h, ctypes.c_uint64), _ptr(p, ctypes.c_uint32),
+                                    _ptr(rd, ctypes.c_uint32), cap,
+                                    _ptr(ro, ctypes.c_uint64))
+    if r < 0:
+        raise ValueError("oracle batch minimizers rejected k=%d w=%d" % (k, w))
+    return h[:r].copy(), p[:r].copy(), rd[:r].copy(), ro

@@ -1,0 +1,348 @@
+/*
+ * oracle.c -- plain, slow, obviously correct CPU reference for sliding window
+ * sums and minimizer seed tables (Snytsar & Turakhia, "Parallel approach to
+ * sliding window sums", arXiv:1811.10074).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library or its product path may
+ * include, link or call this file.  It shares no header, table, constant or
+ * helper with the HIP implementation; every constant below is typed here from
+ * its own definition.  Only tests, the smoke check and the benchmark's CPU
+ * baseline leg use it.
+ *
+ * Every routine is the plain definition written out, with no blocking,
+ * reordering or fusion beyond what that definition states:
+ *
+ *   oracle_sliding_sum        Sec. 2.2, Eq. 2: y_i = x_i (+) ... (+) x_{i+w-1},
+ *                             exactly w addends, as a left fold (the naive
+ *                             O(wN) algorithm of Sec. 2.2).
+ *   oracle_kmers              Sec. 2.4: k-mers as a sliding sum of bases under
+ *                             concatenation, written as the positional value
+ *                             sum_j code(s_{i+j}) * 4^(k-1-j); the reverse
+ *                             complement likewise; canonical = the smaller.
+ *   oracle_mix64(_inv)        the fixed invertible xorshift-multiply hash used
+ *                             for "hashed k-mers" (Sec. 4).  The paper names
+ *                             no hash: parity unpinned against the paper; it is
+ *                             pinned only to its own definition (known answers
+ *                             and the inverse).
+ *   oracle_minimizers_naive   Sec. 2.4 / Fig. 2: for every window of w
+ *                             consecutive k-mers, the minimum (hash, position)
+ *                             pair, leftmost on ties; adjacent windows with the
+ *                             same pair are stored once.  O(w) per window.
+ *   oracle_minimizers_deque   the same result with the monotone-deque sliding
+ *                             minimum the paper cites as the O(N) alternative
+ *                             (Sec. 2.4, "Dequeue" in Sec. 4 / Fig. 3).
+ *   oracle_minimizers_batch   the deque routine run once per read.
+ *
+ * Readings of points the paper leaves open (stated once here, used below):
+ *   - identity of each operator pads nothing: the naive fold never needs it;
+ *   - bases A/C/G/T (either case) code as 0/1/2/3 (lexicographic order, Sec.
+ *     2.4); any other byte is invalid and a k-mer covering it is invalid;
+ *   - an invalid k-mer never wins a window; a window with no valid k-mer
+ *     stores nothing; positions are 0-based k-mer start offsets;
+ *   - n < w (or fewer than w k-mers) gives no output at all.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Operator codes understood by oracle_sliding_sum. */
+#define ORC_ADD 0
+#define ORC_MIN 1
+#define ORC_MAX 2
+#define ORC_AFFINE 3
+
+/* Minimizer flags understood by the oracle. */
+#define ORC_FORWARD 1u  /* use the forward k-mer instead of the canonical one */
+#define ORC_IDENTITY 2u /* use the k-mer value itself instead of its hash    */
+
+/* ---------------------------------------------------------------------- */
+/* Sec. 2.2, Eq. 2: the sliding window sum, one left fold of w addends.     */
+/* ---------------------------------------------------------------------- */
+
+/* The affine maps f(z) = a*z + b (mod 2^32), stored as pairs (a, b).
+ * (a,b) (+) (c,d) is the composition f_ab(f_cd(z)) = a*c*z + a*d + b. */
+static void affine_combine(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                           uint32_t *ra, uint32_t *rb) {
+    *ra = (uint32_t)(a * c);
+    *rb = (uint32_t)(a * d + b);
+}
+
+/* Returns the number of outputs (n - w + 1, or 0 when n < w), or -1 when the
+ * operator is unknown or w is 0.  For ORC_AFFINE, x holds n interleaved
+ * (a, b) pairs and y receives pairs. */
+long long oracle_sliding_sum(int op, uint64_t w, const uint32_t *x, uint64_t n,
+                             uint32_t *y) {
+    if (w == 0 || op < ORC_ADD || op > ORC_AFFINE) return -1;
+    if (n < w) return 0;
+    uint64_t count = n - w + 1;
+    for (uint64_t i = 0; i < count; ++i) {
+        if (op == ORC_AFFINE) {
+            uint32_t a = x[2 * i], b = x[2 * i + 1];
+            for (uint64_t j = 1; j < w; ++j) {
+                uint32_t na, nb;
+                affine_combine(a, b, x[2 * (i + j)], x[2 * (i + j) + 1], &na, &nb);
+                a = na;
+                b = nb;
+            }
+            y[2 * i] = a;
+            y[2 * i + 1] = b;
+        } else {
+            uint32_t acc = x[i];
+            for (uint64_t j = 1; j < w; ++j) {
+                uint32_t v = x[i + j];
+                if (op == ORC_ADD) acc = (uint32_t)(acc + v);
+                else if (op == ORC_MIN) acc = v < acc ? v : acc;
+                else acc = v > acc ? v : acc;
+            }
+            y[i] = acc;
+        }
+    }
+    return (long long)count;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The hash: x ^= x>>32; x *= C1; x ^= x>>29; x *= C2; x ^= x>>32 (mod 2^64) */
+/* C1 = floor(2^64 * (golden ratio - 1)), C2 = floor(2^64 * (pi - 3)).       */
+/* ---------------------------------------------------------------------- */
+static const uint64_t ORC_C1 = 0x9E3779B97F4A7C15ull;
+static const uint64_t ORC_C2 = 0x243F6A8885A308D3ull;
+static const uint64_t ORC_C1_INV = 0xF1DE83E19937733Dull; /* C1 * C1_INV == 1 */
+static const uint64_t ORC_C2_INV = 0xFBF07FAC8BAA8F5Bull; /* C2 * C2_INV == 1 */
+
+uint64_t oracle_mix64(uint64_t x) {
+    x ^= x >> 32;
+    x *= ORC_C1;
+    x ^= x >> 29;
+    x *= ORC_C2;
+    x ^= x >> 32;
+    return x;
+}
+
+/* Undo each step in reverse order.  y ^= y>>29 is undone by
+ * y ^= (y>>29) ^ (y>>58), since two applications of the shift reach past 64. */
+uint64_t oracle_mix64_inv(uint64_t y) {
+    y ^= y >> 32;
+    y *= ORC_C2_INV;
+    y ^= (y >> 29) ^ (y >> 58);
+    y *= ORC_C1_INV;
+    y ^= y >> 32;
+    return y;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sec. 2.4: bases, k-mers, canonical k-mers.                              */
+/* ---------------------------------------------------------------------- */
+
+/* A=0, C=1, G=2, T=3 (either case); -1 for every other byte. */
+int oracle_base_code(uint8_t c) {
+    switch (c) {
+    case 'A': case 'a': return 0;
+    case 'C': case 'c': return 1;
+    case 'G': case 'g': return 2;
+    case 'T': case 't': return 3;
+    default: return -1;
+    }
+}
+
+/* The k-mer starting at i, its validity, forward value and reverse-complement
+ * value, each straight from the positional definition. */
+static int kmer_at(const uint8_t *seq, uint64_t i, uint32_t k, uint64_t *fwd,
+                   uint64_t *rc) {
+    uint64_t f = 0, r = 0, place = 1;
+    for (uint32_t j = 0; j < k; ++j) {
+        int c = oracle_base_code(seq[i + j]);
+        if (c < 0) return 0;
+        f = f * 4u + (uint64_t)c;             /* sum_j code * 4^(k-1-j)    */
+        r = r + (uint64_t)(3 - c) * place;    /* sum_j (3 - code) * 4^j    */
+        place *= 4u;
+    }
+    *fwd = f;
+    *rc = r;
+    return 1;
+}
+
+/* The value a k-mer contributes under the flags: forward or canonical, then
+ * hashed or not. */
+static uint64_t kmer_value(uint64_t fwd, uint64_t rc, uint32_t flags) {
+    uint64_t v = fwd;
+    if (!(flags & ORC_FORWARD) && rc < fwd) v = rc;
+    if (!(flags & ORC_IDENTITY)) v = oracle_mix64(v);
+    return v;
+}
+
+/* out[i] = value of the k-mer at i, or UINT64_MAX when it covers an invalid
+ * base.  Returns n - k + 1 (0 when n < k), or -1 for k outside [1, 31]. */
+long long oracle_kmers(const uint8_t *seq, uint64_t n, uint32_t k, uint32_t flags,
+                       uint64_t *out) {
+    if (k < 1 || k > 31) return -1;
+    if (n < k) return 0;
+    uint64_t nk = n - k + 1;
+    for (uint64_t i = 0; i < nk; ++i) {
+        uint64_t f, r;
+        out[i] = kmer_at(seq, i, k, &f, &r) ? kmer_value(f, r, flags) : UINT64_MAX;
+    }
+    return (long long)nk;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sec. 2.4 / Fig. 2: minimizers of windows of w consecutive k-mers.        */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    uint64_t h;
+    uint64_t pos;
+    int valid;
+} orc_key;
+
+/* Hash (or value) and validity of every k-mer of seq[0, n). */
+static orc_key *all_keys(const uint8_t *seq, uint64_t n, uint32_t k, uint32_t flags,
+                         uint64_t *nk_out) {
+    uint64_t nk = n >= k ? n - k + 1 : 0;
+    orc_key *keys = (orc_key *)malloc((nk ? nk : 1) * sizeof(orc_key));
+    if (!keys) return NULL;
+    for (uint64_t i = 0; i < nk; ++i) {
+        uint64_t f, r;
+        keys[i].pos = i;
+        keys[i].valid = kmer_at(seq, i, k, &f, &r);
+        keys[i].h = keys[i].valid ? kmer_value(f, r, flags) : 0;
+    }
+    *nk_out = nk;
+    return keys;
+}
+
+/* Lexicographic order on (hash, position): a is strictly smaller than b. */
+static int key_less(const orc_key *a, const orc_key *b) {
+    if (a->h != b->h) return a->h < b->h;
+    return a->pos < b->pos;
+}
+
+/* The previous window's minimum, compared as a whole (hash and position). */
+typedef struct {
+    uint64_t h;
+    uint64_t pos;
+    int some; /* 0: no previous window, or the previous window was empty */
+} orc_prev;
+
+/* Store one window minimum unless it equals the previous window's. */
+static void emit(uint64_t h, uint64_t pos, orc_prev *prev, uint64_t *count,
+                 uint64_t *out_hash, uint32_t *out_pos, uint32_t *out_read,
+                 uint32_t read, uint64_t cap) {
+    int same = prev->some && prev->h == h && prev->pos == pos;
+    prev->h = h;
+    prev->pos = pos;
+    prev->some = 1;
+    if (same) return;
+    if (*count < cap) {
+        out_hash[*count] = h;
+        out_pos[*count] = (uint32_t)pos;
+        if (out_read) out_read[*count] = read;
+    }
+    *count += 1;
+}
+
+static int check_args(uint32_t k, uint32_t w, uint32_t flags) {
+    return k >= 1 && k <= 31 && w >= 1 && (flags & ~(ORC_FORWARD | ORC_IDENTITY)) == 0;
+}
+
+/* O(w) per window.  Returns the number of minimizers (entries beyond cap are
+ * counted but not written), or -1 for bad arguments / -3 when out of memory. */
+long long oracle_minimizers_naive(const uint8_t *seq, uint64_t n, uint32_t k,
+                                  uint32_t w, uint32_t flags, uint64_t *out_hash,
+                                  uint32_t *out_pos, uint64_t cap) {
+    if (!check_args(k, w, flags)) return -1;
+    uint64_t nk;
+    orc_key *keys = all_keys(seq, n, k, flags, &nk);
+    if (!keys) return -3;
+    uint64_t count = 0;
+    orc_prev prev = {0, 0, 0};
+    if (nk >= w) {
+        for (uint64_t p = 0; p + w <= nk; ++p) {
+            const orc_key *best = NULL;
+            for (uint64_t j = p; j < p + w; ++j) {
+                if (!keys[j].valid) continue;
+                if (best == NULL || key_less(&keys[j], best)) best = &keys[j];
+            }
+            if (best == NULL) { /* no valid k-mer: nothing stored */
+                prev.some = 0;
+                continue;
+            }
+            emit(best->h, best->pos, &prev, &count, out_hash, out_pos, NULL, 0, cap);
+        }
+    }
+    free(keys);
+    return (long long)count;
+}
+
+/* Windows of one read, deque variant.  Appends to the outputs at *count. */
+static int deque_windows(const uint8_t *seq, uint64_t n, uint32_t k, uint32_t w,
+                         uint32_t flags, uint64_t *out_hash, uint32_t *out_pos,
+                         uint32_t *out_read, uint32_t read, uint64_t cap,
+                         uint64_t *count) {
+    uint64_t nk;
+    orc_key *keys = all_keys(seq, n, k, flags, &nk);
+    if (!keys) return -3;
+    uint64_t *dq = (uint64_t *)malloc((nk ? nk : 1) * sizeof(uint64_t));
+    if (!dq) {
+        free(keys);
+        return -3;
+    }
+    uint64_t head = 0, tail = 0; /* deque = dq[head, tail), keys increasing */
+    orc_prev prev = {0, 0, 0};
+    for (uint64_t i = 0; i < nk; ++i) {
+        if (keys[i].valid) {
+            while (tail > head && key_less(&keys[i], &keys[dq[tail - 1]])) --tail;
+            dq[tail++] = i;
+        }
+        if (i + 1 >= w) {
+            uint64_t p = i + 1 - w; /* window p covers k-mers p .. i */
+            while (tail > head && dq[head] < p) ++head;
+            if (tail == head) { /* no valid k-mer in the window */
+                prev.some = 0;
+                continue;
+            }
+            const orc_key *m = &keys[dq[head]];
+            emit(m->h, m->pos, &prev, count, out_hash, out_pos, out_read, read, cap);
+        }
+    }
+    free(dq);
+    free(keys);
+    return 0;
+}
+
+/* Amortized O(1) per window (monotone deque).  Same contract as the naive
+ * routine. */
+long long oracle_minimizers_deque(const uint8_t *seq, uint64_t n, uint32_t k,
+                                  uint32_t w, uint32_t flags, uint64_t *out_hash,
+                                  uint32_t *out_pos, uint64_t cap) {
+    if (!check_args(k, w, flags)) return -1;
+    uint64_t count = 0;
+    int rc = deque_windows(seq, n, k, w, flags, out_hash, out_pos, NULL, 0, cap, &count);
+    return rc ? rc : (long long)count;
+}
+
+/* Reads r = 0 .. nreads-1 occupy seqs[offsets[r], offsets[r+1]).  Each read is
+ * handled on its own: positions are relative to the read start and no window
+ * spans two reads.  read_offsets[r] receives the index of read r's first
+ * minimizer and read_offsets[nreads] the total.  Returns the total count. */
+long long oracle_minimizers_batch(const uint8_t *seqs, const uint64_t *offsets,
+                                  uint32_t nreads, uint32_t k, uint32_t w,
+                                  uint32_t flags, uint64_t *out_hash,
+                                  uint32_t *out_pos, uint32_t *out_read,
+                                  uint64_t cap, uint64_t *read_offsets) {
+    if (!check_args(k, w, flags)) return -1;
+    uint64_t count = 0;
+    for (uint32_t r = 0; r < nreads; ++r) {
+        if (offsets[r + 1] < offsets[r]) return -1;
+        read_offsets[r] = count;
+        int rc = deque_windows(seqs + offsets[r], offsets[r + 1] - offsets[r], k, w,
+                               flags, out_hash, out_pos, out_read, r, cap, &count);
+        if (rc) return rc;
+    }
+    read_offsets[nreads] = count;
+    return (long long)count;
+}
+
+/* Element-wise mix64 (inverse = 0) or its inverse (inverse = 1) over an array. */
+void oracle_mix64_array(const uint64_t *x, uint64_t n, int inverse, uint64_t *y) {
+    for (uint64_t i = 0; i < n; ++i) y[i] = inverse ? oracle_mix64_inv(x[i]) : oracle_mix64(x[i]);
+}

@@ -1,0 +1,56 @@
+"""Planted mistakes in the oracle are caught by the pins.
+
+Each mutant is a copy of oracle.c with one plausible mistake (a dropped term,
+a transposed operand, a wrong comparison or index), compiled with gcc into a
+temporary library.  The pins in oracle_pins.py must reject every one of them.
+"""
+import os
+
+import pytest
+
+import oracle
+import oracle_pins
+
+MUTANTS = {
+    "affine_transposed": ("*rb = (uint32_t)(a * d + b);", "*rb = (uint32_t)(c * b + d);"),
+    "affine_dropped_term": ("*rb = (uint32_t)(a * d + b);", "*rb = (uint32_t)(a * d);"),
+    "fold_short_window": ("uint32_t acc = x[i];\n            for (uint64_t j = 1; j < w; ++j)",
+                          "uint32_t acc = x[i];\n            for (uint64_t j = 1; j + 1 < w; ++j)"),
+    "min_as_max": ("acc = v < acc ? v : acc;", "acc = v > acc ? v : acc;"),
+    "add_carry_lost": ("acc = (uint32_t)(acc + v);", "acc = (uint32_t)(acc | v);"),
+    "revcomp_no_complement": ("r = r + (uint64_t)(3 - c) * place;", "r = r + (uint64_t)c * place;"),
+    "canonical_max": ("if (!(flags & ORC_FORWARD) && rc < fwd) v = rc;",
+                      "if (!(flags & ORC_FORWARD) && rc > fwd) v = rc;"),
+    "hash_shift": ("    x ^= x >> 29;\n    x *= ORC_C2;", "    x ^= x >> 28;\n    x *= ORC_C2;"),
+    "hash_constant": ("ORC_C1 = 0x9E3779B97F4A7C15ull", "ORC_C1 = 0x9E3779B97F4A7C17ull"),
+    "naive_window_short": ("for (uint64_t j = p; j < p + w; ++j)", "for (uint64_t j = p; j + 1 < p + w; ++j)"),
+    "tie_rightmost": ("return a->pos < b->pos;", "return a->pos > b->pos;"),
+    "deque_pops_ties": ("while (tail > head && key_less(&keys[i], &keys[dq[tail - 1]])) --tail;",
+                        "while (tail > head && keys[i].h <= keys[dq[tail - 1]].h) --tail;"),
+    "no_dedup": ("    if (same) return;\n", "\n"),
+    "deque_window_off_by_one": ("uint64_t p = i + 1 - w;", "uint64_t p = i + 2 - w;"),
+    "invalid_base_ignored": ("if (c < 0) return 0;", "if (c < 0) c = 0;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle._SRC).read()
+    assert src.count(old) >= 1, "mutation site vanished: " + name
+    mutated = tmp_path / "oracle_mutant.c"
+    mutated.write_text(src.replace(old, new, 1))
+    so = str(tmp_path / ("liboracle_%s.so" % name))
+    oracle.build(out=so, src=str(mutated), extra_flags=("-w",))
+    lib = oracle.load(path=so)
+    caught = []
+    for pin in oracle_pins.ALL_PINS:
+        try:
+            pin(lib)
+        except AssertionError:
+            caught.append(pin.__name__)
+            break
+        except (ValueError, IndexError):
+            caught.append(pin.__name__)
+            break
+    assert caught, "mutant %s passed every pin" % name
