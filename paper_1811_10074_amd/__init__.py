@@ -1,0 +1,176 @@
+"""sws: sliding window sums and minimizer seed tables on AMD MI355X (gfx950).
+
+A thin binding over libsws.so (include/sws.h): every step runs in the HIP
+kernels; this module only allocates torch tensors for device memory, passes
+pointers and the current torch stream, and maps status codes to exceptions.
+
+    sliding_sum(op, w, x, path="auto")   Sec. 2.2 Eq. 2 (op: add/min/max/affine)
+    pack2bit(seq)                         2-bit codes + invalid bits
+    kmers(seq, k, canonical, hashed)      one value per k-mer (UINT64_MAX if invalid)
+    minimizers(seq, k, w, ...)            Sec. 2.4 / Fig. 2 seeds: (hash, pos)
+    minimizers_2bit(packed, invalid, n, k, w, ...)
+    minimizers_batch(seqs, offsets, k, w, ...)
+
+Device tensors hold unsigned data in signed torch dtypes (int32 for uint32,
+int64 for uint64); ``.view(numpy.uint32)`` etc. on the host restores the
+unsigned reading.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import SwsError, check
+
+__all__ = ["sliding_sum", "pack2bit", "kmers", "minimizers", "minimizers_2bit",
+           "minimizers_batch", "MinimizerRunner", "window_bound", "SwsError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _need_cuda(t, name):
+    if not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def _flags(canonical: bool, hashed: bool) -> int:
+    return (0 if canonical else _lib.KMER_FORWARD) | (0 if hashed else _lib.HASH_IDENTITY)
+
+
+def window_bound(n: int, k: int, w: int) -> int:
+    """Most minimizers a sequence of n bases can have."""
+    return max(0, n - k - w + 2)
+
+
+def sliding_sum(op: str, w: int, x, path: str = "auto", out=None):
+    """y_i = x_i (+) ... (+) x_{i+w-1}.  x: int32/uint32 tensor [n], or [n, 2]
+    (a, b) pairs for op='affine'.  Returns a tensor of n-w+1 elements."""
+    torch = _torch()
+    _need_cuda(x, "x")
+    if op not in _lib.OPS:
+        raise ValueError("unknown op %r" % op)
+    if path not in _lib.PATHS:
+        raise ValueError("unknown path %r" % path)
+    if x.element_size() != 4:
+        raise ValueError("x must hold 32-bit elements")
+    pair = op == "affine"
+    if pair and (x.dim() != 2 or x.shape[1] != 2):
+        raise ValueError("affine input must have shape [n, 2]")
+    n = x.shape[0]
+    cnt = max(0, n - w + 1) if w >= 1 else 0
+    shape = (cnt, 2) if pair else (cnt,)
+    if out is None:
+        out = torch.empty(shape, dtype=x.dtype, device=x.device)
+    elif tuple(out.shape) != shape or out.dtype != x.dtype:
+        raise ValueError("out must have shape %s and dtype %s" % (shape, x.dtype))
+    st = _lib.load().sws_sliding_sum_ex(_lib.OPS[op], w, _ptr(x), n, _ptr(out),
+                                         _lib.PATHS[path], _stream())
+    check(st, "sws_sliding_sum_ex")
+    return out
+
+
+def pack2bit(seq, with_invalid: bool = True):
+    """ASCII uint8 tensor -> (packed int32[ceil(n/16)], invalid int32[ceil(n/32)] or None)."""
+    torch = _torch()
+    _need_cuda(seq, "seq")
+    n = seq.numel()
+    packed = torch.empty((n + 15) // 16, dtype=torch.int32, device=seq.device)
+    invalid = torch.empty((n + 31) // 32, dtype=torch.int32, device=seq.device) if with_invalid else None
+    check(_lib.load().sws_pack2bit(_ptr(seq), n, _ptr(packed), _ptr(invalid), _stream()),
+          "sws_pack2bit")
+    return packed, invalid
+
+
+def kmers(seq, k: int, canonical: bool = True, hashed: bool = True):
+    torch = _torch()
+    _need_cuda(seq, "seq")
+    n = seq.numel()
+    out = torch.empty(max(0, n - k + 1), dtype=torch.int64, device=seq.device)
+    check(_lib.load().sws_kmers(_ptr(seq), n, k, _flags(canonical, hashed), _ptr(out), _stream()),
+          "sws_kmers")
+    return out
+
+
+def minimizer_workspace_bytes(n: int, k: int, w: int) -> int:
+    b = ctypes.c_uint64(0)
+    check(_lib.load().sws_minimizers_workspace(n, k, w, ctypes.byref(b)), "sws_minimizers_workspace")
+    return int(b.value)
+
+
+class MinimizerRunner:
+    """Preallocated outputs and workspace for repeated minimizer calls on
+    sequences of up to ``max_n`` bases (no allocation per call)."""
+
+    def __init__(self, max_n: int, k: int, w: int, device="cuda"):
+        torch = _torch()
+        self.k, self.w, self.max_n = k, w, max_n
+        self.capacity = window_bound(max_n, k, w)
+        self.hash = torch.empty(max(self.capacity, 1), dtype=torch.int64, device=device)
+        self.pos = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+        ws = minimizer_workspace_bytes(max_n, k, w)
+        self.workspace = torch.empty(max(ws, 8), dtype=torch.uint8, device=device)
+
+    def launch(self, seq=None, packed=None, invalid=None, n=None, canonical=True, hashed=True):
+        """Enqueue one call on the current stream; results stay on the device
+        (self.hash, self.pos, self.count)."""
+        lib = _lib.load()
+        fl = _flags(canonical, hashed)
+        if seq is not None:
+            n = seq.numel()
+            if n > self.max_n:
+                raise ValueError("sequence longer than the runner's max_n")
+            st = lib.sws_minimizers(_ptr(seq), n, self.k, self.w, fl, _ptr(self.hash),
+                                    _ptr(self.pos), self.capacity, _ptr(self.count),
+                                    _ptr(self.workspace), self.workspace.numel(), _stream())
+            check(st, "sws_minimizers")
+        else:
+            if n is None or n > self.max_n:
+                raise ValueError("n missing or above max_n")
+            st = lib.sws_minimizers_2bit(_ptr(packed), _ptr(invalid), n, self.k, self.w, fl,
+                                         _ptr(self.hash), _ptr(self.pos), self.capacity,
+                                         _ptr(self.count), _ptr(self.workspace),
+                                         self.workspace.numel(), _stream())
+            check(st, "sws_minimizers_2bit")
+
+    def result(self):
+        """Synchronizes, then returns (hash int64[c], pos int32[c]) views."""
+        c = int(self.count.item())
+        return self.hash[:c], self.pos[:c]
+
+
+def minimizers(seq, k: int, w: int, canonical: bool = True, hashed: bool = True):
+    """Deduplicated minimizers of one ASCII sequence: (hash int64[c], pos int32[c])."""
+    _need_cuda(seq, "seq")
+    r = MinimizerRunner(seq.numel(), k, w, device=seq.device)
+    r.launch(seq=seq, canonical=canonical, hashed=hashed)
+    h, p = r.result()
+    return h.clone(), p.clone()
+
+
+def minimizers_2bit(packed, invalid, n: int, k: int, w: int, canonical: bool = True,
+                    hashed: bool = True):
+    _need_cuda(packed, "packed")
+    r = MinimizerRunner(n, k, w, device=packed.device)
+    r.launch(packed=packed, invalid=invalid, n=n, canonical=canonical, hashed=hashed)
+    h, p = r.result()
+    return h.clone(), p.clone()
+
+
+def minimizers_batch(seqs, offsets, k: int, w: int, canonical: bool = True, hashed: bool = True):
+    from .batch import minimizers_batch as _mb
+    return _mb(seqs, offsets, k, w, canonical=canonical, hashed=hashed)

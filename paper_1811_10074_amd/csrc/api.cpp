@@ -1,0 +1,215 @@
+// api.cpp -- the extern "C" entry points of libsws (declared in sws.h): host-side
+// validation, path choice and launch.  Nothing here touches device memory
+// before every argument has been checked; nothing here allocates or waits.
+#include "sws.h"
+
+#include <stdint.h>
+#include <string.h>
+
+#include "sws_internal.hpp"
+
+namespace {
+
+bool known_flags(uint32_t flags) {
+    return (flags & ~(uint32_t)(SWS_KMER_FORWARD | SWS_HASH_IDENTITY)) == 0u;
+}
+
+// Threads per workgroup of the minimizer kernels, per read-length bucket.
+uint32_t g_min_block[3] = {256, 256, 256};
+
+uint32_t bucket_of(uint64_t total_bases, uint64_t nreads) {
+    const uint64_t mean = nreads ? total_bases / nreads : total_bases;
+    return mean < 1000 ? 0u : (mean < 16000 ? 1u : 2u);
+}
+
+// Smallest tile (most tiles) over the block sizes the library may use: the
+// workspace bound must hold whatever the tuner picks later.
+uint64_t max_tiles(uint64_t nwin, uint32_t w) {
+    const uint32_t tw = sws::minimizer_tile_windows(128, w);
+    if (tw == 0) return 0;
+    return (nwin + tw - 1) / tw;
+}
+
+constexpr uint32_t kMaxMinimizerWindow = 1024;  // keys per wavefront
+constexpr uint64_t kMaxPositions = 0xFFFFFFFEull;
+
+int check_minimizer_args(uint64_t n, uint32_t k, uint32_t w, uint32_t flags) {
+    if (k < 1 || k > 31 || w < 1 || !known_flags(flags)) return SWS_ERR_INVALID;
+    if (w > kMaxMinimizerWindow) return SWS_ERR_UNSUPPORTED;
+    if (n >= kMaxPositions) return SWS_ERR_UNSUPPORTED;
+    return SWS_OK;
+}
+
+uint64_t window_count(uint64_t n, uint32_t k, uint32_t w) {
+    const uint64_t need = (uint64_t)k + w - 1;
+    return n >= need ? n - need + 1 : 0;
+}
+
+int minimizers_common(const sws::GenomeInput& in, uint64_t n, uint32_t k, uint32_t w,
+                      uint32_t flags, uint64_t* out_hash, uint32_t* out_pos, uint64_t capacity,
+                      uint64_t* d_count, void* workspace, uint64_t ws_bytes, hipStream_t s) {
+    int st = check_minimizer_args(n, k, w, flags);
+    if (st != SWS_OK) return st;
+    if (d_count == nullptr) return SWS_ERR_INVALID;
+    const uint64_t nwin = window_count(n, k, w);
+    if (nwin > 0 && (out_hash == nullptr || out_pos == nullptr)) return SWS_ERR_INVALID;
+    if (capacity < nwin) return SWS_ERR_CAPACITY;
+    const uint32_t nt = g_min_block[bucket_of(n, 1)];
+    const uint32_t tw = sws::minimizer_tile_windows(nt, w);
+    const uint64_t ntiles = nwin ? (nwin + tw - 1) / tw : 0;
+    const uint64_t need = sws::minimizer_workspace_bytes(max_tiles(nwin, w));
+    if (workspace == nullptr || ws_bytes < need || ((uintptr_t)workspace & 7u)) return SWS_ERR_WORKSPACE;
+    if (nwin == 0) {
+        // nothing to compute; the count is still written on the stream
+        return sws::launch_zero(d_count, 1, s) == 0 ? SWS_OK : SWS_ERR_DEVICE;
+    }
+    sws::MinimizerArgs a;
+    memset(&a, 0, sizeof(a));
+    a.k = k;
+    a.w = w;
+    a.flags = flags;
+    a.tw = tw;
+    a.nwin = nwin;
+    a.ntiles = ntiles;
+    a.out_hash = out_hash;
+    a.out_pos = out_pos;
+    a.capacity = capacity;
+    a.d_count = d_count;
+    return sws::launch_minimizers(in, a, nt, workspace, s) == 0 ? SWS_OK : SWS_ERR_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t sws_abi_version(void) { return SWS_ABI_VERSION; }
+
+const char* sws_status_str(int status) {
+    switch (status) {
+    case SWS_OK: return "SWS_OK";
+    case SWS_ERR_INVALID: return "SWS_ERR_INVALID: invalid argument";
+    case SWS_ERR_CAPACITY: return "SWS_ERR_CAPACITY: output capacity too small";
+    case SWS_ERR_WORKSPACE: return "SWS_ERR_WORKSPACE: workspace missing, misaligned or too small";
+    case SWS_ERR_DEVICE: return "SWS_ERR_DEVICE: kernel launch failed";
+    case SWS_ERR_UNSUPPORTED: return "SWS_ERR_UNSUPPORTED: request not served by this build";
+    default: return "unknown sws status";
+    }
+}
+
+int sws_sliding_sum_ex(int op, uint64_t w, const void* x, uint64_t n, void* y, int path,
+                       hipStream_t s) {
+    if (op < SWS_OP_ADD_U32 || op > SWS_OP_AFFINE_U32) return SWS_ERR_INVALID;
+    if (path < SWS_PATH_AUTO || path > SWS_PATH_LOG) return SWS_ERR_INVALID;
+    if (w == 0) return SWS_ERR_INVALID;
+    const bool idem = op == SWS_OP_MIN_U32 || op == SWS_OP_MAX_U32;
+    if (path == SWS_PATH_LOG && !idem) return SWS_ERR_UNSUPPORTED;
+    if (n < w) return SWS_OK;
+    if (x == nullptr || y == nullptr) return SWS_ERR_INVALID;
+    const uintptr_t align = op == SWS_OP_AFFINE_U32 ? 8u : 4u;
+    if (((uintptr_t)x | (uintptr_t)y) & (align - 1u)) return SWS_ERR_INVALID;
+    const uint64_t count = n - w + 1;
+    int use = path;
+    if (use == SWS_PATH_AUTO) use = SWS_PATH_GENERIC;
+    if (use == SWS_PATH_LOG) {
+        if (w > sws::log_max_window()) return SWS_ERR_UNSUPPORTED;
+        return sws::launch_sliding_log(op, x, n, (uint32_t)w, y, count, s) == 0 ? SWS_OK
+                                                                               : SWS_ERR_DEVICE;
+    }
+    if (w > sws::generic_max_window()) return SWS_ERR_UNSUPPORTED;
+    return sws::launch_sliding_generic(op, x, n, (uint32_t)w, y, count, s) == 0 ? SWS_OK
+                                                                               : SWS_ERR_DEVICE;
+}
+
+int sws_sliding_sum(int op, uint64_t w, const void* x, uint64_t n, void* y, hipStream_t s) {
+    return sws_sliding_sum_ex(op, w, x, n, y, SWS_PATH_AUTO, s);
+}
+
+int sws_pack2bit(const uint8_t* seq, uint64_t n, uint32_t* packed, uint32_t* invalid,
+                 hipStream_t s) {
+    if (n == 0) return SWS_OK;
+    if (seq == nullptr || packed == nullptr) return SWS_ERR_INVALID;
+    return sws::launch_pack2bit(seq, n, packed, invalid, s) == 0 ? SWS_OK : SWS_ERR_DEVICE;
+}
+
+int sws_kmers(const uint8_t* seq, uint64_t n, uint32_t k, uint32_t flags, uint64_t* out,
+              hipStream_t s) {
+    if (k < 1 || k > 31 || !known_flags(flags)) return SWS_ERR_INVALID;
+    if (k >= 30 && (flags & SWS_HASH_IDENTITY) == 0u) return SWS_ERR_UNSUPPORTED;
+    if (n < k) return SWS_OK;
+    if (seq == nullptr || out == nullptr) return SWS_ERR_INVALID;
+    if ((uintptr_t)out & 7u) return SWS_ERR_INVALID;
+    sws::GenomeInput in;
+    memset(&in, 0, sizeof(in));
+    in.kind = sws::kInAscii;
+    in.aligned = ((uintptr_t)seq & 15u) == 0;
+    in.seq = seq;
+    in.n = n;
+    return sws::launch_kmers(in, k, flags, out, s) == 0 ? SWS_OK : SWS_ERR_DEVICE;
+}
+
+int sws_minimizers_workspace(uint64_t n, uint32_t k, uint32_t w, uint64_t* bytes) {
+    if (bytes == nullptr) return SWS_ERR_INVALID;
+    const int st = check_minimizer_args(n, k, w, 0);
+    if (st != SWS_OK) return st;
+    *bytes = sws::minimizer_workspace_bytes(max_tiles(window_count(n, k, w), w));
+    return SWS_OK;
+}
+
+int sws_minimizers(const uint8_t* seq, uint64_t n, uint32_t k, uint32_t w, uint32_t flags,
+                   uint64_t* out_hash, uint32_t* out_pos, uint64_t capacity, uint64_t* d_count,
+                   void* workspace, uint64_t ws_bytes, hipStream_t s) {
+    if (n > 0 && seq == nullptr) return SWS_ERR_INVALID;
+    sws::GenomeInput in;
+    memset(&in, 0, sizeof(in));
+    in.kind = sws::kInAscii;
+    in.aligned = ((uintptr_t)seq & 15u) == 0;
+    in.seq = seq;
+    in.n = n;
+    return minimizers_common(in, n, k, w, flags, out_hash, out_pos, capacity, d_count, workspace,
+                             ws_bytes, s);
+}
+
+int sws_minimizers_2bit(const uint32_t* packed, const uint32_t* invalid, uint64_t n, uint32_t k,
+                        uint32_t w, uint32_t flags, uint64_t* out_hash, uint32_t* out_pos,
+                        uint64_t capacity, uint64_t* d_count, void* workspace, uint64_t ws_bytes,
+                        hipStream_t s) {
+    if (n > 0 && packed == nullptr) return SWS_ERR_INVALID;
+    if (((uintptr_t)packed | (uintptr_t)invalid) & 3u) return SWS_ERR_INVALID;
+    sws::GenomeInput in;
+    memset(&in, 0, sizeof(in));
+    in.kind = sws::kIn2bit;
+    in.packed = packed;
+    in.invalid = invalid;
+    in.n = n;
+    return minimizers_common(in, n, k, w, flags, out_hash, out_pos, capacity, d_count, workspace,
+                             ws_bytes, s);
+}
+
+int sws_minimizers_batch_workspace(uint64_t total_bases, uint32_t nreads, uint32_t k, uint32_t w,
+                                   uint64_t* bytes) {
+    (void)total_bases;
+    (void)nreads;
+    (void)k;
+    (void)w;
+    if (bytes == nullptr) return SWS_ERR_INVALID;
+    return SWS_ERR_UNSUPPORTED;
+}
+
+int sws_minimizers_batch(const uint8_t* seqs, const uint64_t* d_offsets, uint32_t nreads,
+                         uint64_t total_bases, uint32_t k, uint32_t w, uint32_t flags,
+                         uint64_t* out_hash, uint32_t* out_pos, uint32_t* out_read,
+                         uint64_t capacity, uint64_t* d_read_out_offsets, void* workspace,
+                         uint64_t ws_bytes, hipStream_t s) {
+    (void)seqs; (void)d_offsets; (void)nreads; (void)total_bases; (void)k; (void)w; (void)flags;
+    (void)out_hash; (void)out_pos; (void)out_read; (void)capacity; (void)d_read_out_offsets;
+    (void)workspace; (void)ws_bytes; (void)s;
+    return SWS_ERR_UNSUPPORTED;
+}
+
+int sws_set_minimizer_block(uint32_t bucket, uint32_t threads) {
+    if (bucket > 2 || (threads != 128 && threads != 256 && threads != 512)) return SWS_ERR_INVALID;
+    g_min_block[bucket] = threads;
+    return SWS_OK;
+}
+
+}  // extern "C"

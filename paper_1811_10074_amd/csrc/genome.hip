@@ -1,0 +1,553 @@
+// genome.hip -- 2-bit packing, k-mers and minimizer seeds (Sec. 2.4, Fig. 2)
+// on gfx950.
+//
+// Sec. 2.4 reads k-mers as a sliding sum of bases under concatenation and a
+// minimizer table as a sliding minimum over k-mers.  One fused pass per tile
+// does every step with no intermediate array in HBM:
+//
+//   1. stage the tile's bases in LDS as 2-bit codes plus an invalid bit
+//      (from ASCII or from the packed layout);
+//   2. each lane forms the k-mers of its 16 positions: the forward value by
+//      the shift-or recurrence f_{i+1} = (f_i << 2 | c_{i+k}) mod 4^k (the
+//      sliding concatenation), the reverse complement by the mirrored
+//      recurrence, the canonical k-mer as the smaller, then mix64;
+//      validity of every k-mer is an OR over k invalid bits, done by doubling
+//      with two overlapping halves (the idempotent case of Sec. 3.1 on bits);
+//   3. the sliding minimum over w keys (value, position): the block
+//      prefix/suffix scheme of the sliding-sum kernels with the
+//      "leftmost minimum" operator, which is associative;
+//   4. a window's minimizer is stored iff it exists and its position differs
+//      from the previous window's (same position <=> same pair);
+//   5. ordered compaction: a block scan of the per-lane store counts, then a
+//      decoupled look-back over the tiles (tile ids from an atomic counter, so
+//      a tile only waits for tiles that are already running), then coalesced
+//      stores from an LDS staging area.
+//
+// Tile geometry: 16 positions per lane, P = 16 * NT key positions per tile
+// starting at K0 = p0 - 16, where p0 (a multiple of 16) is the first window
+// the tile stores; it owns windows [p0, p0 + TW).  The 16 extra keys give
+// the window before p0, whose minimizer the dedup test needs.
+#include "sws_device.hpp"
+#include "sws_internal.hpp"
+#include "sws_scan.hpp"
+
+namespace sws {
+
+constexpr int kR = 16;                    // positions per lane
+constexpr uint32_t kInvalidTag = 0x8000u; // tag bit: key of an invalid k-mer
+
+// ---------------------------------------------------------------------------
+// Bases.
+// ---------------------------------------------------------------------------
+
+// A/a=0 C/c=1 G/g=2 T/t=3: bits 1..2 of the byte, xor-folded.
+__device__ __forceinline__ uint32_t base_code(uint32_t b) { return ((b >> 1) ^ (b >> 2)) & 3u; }
+__device__ __forceinline__ bool base_valid(uint32_t b) {
+    const uint32_t u = b & 0xDFu;
+    return u == 'A' || u == 'C' || u == 'G' || u == 'T';
+}
+
+// 16 bases starting at `base` (may be negative or run past n): the code word
+// (first base in bits 31..30) and 16 invalid bits (bit i = base + i).  Bases
+// outside [0, n) are invalid with code 0.  Invalid bases get code 0.
+__device__ __forceinline__ void ascii16(const uint8_t* __restrict__ seq, int64_t base, uint64_t n,
+                                        bool aligned, uint32_t& code, uint32_t& inv) {
+    uint32_t word[4];
+    if (aligned && base >= 0 && (uint64_t)base + 16 <= n) {
+        const uint4 q = *reinterpret_cast<const uint4*>(seq + base);
+        word[0] = q.x;
+        word[1] = q.y;
+        word[2] = q.z;
+        word[3] = q.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int64_t g = base + i * 4 + b;
+                const uint32_t byte = (g >= 0 && (uint64_t)g < n) ? (uint32_t)seq[g] : 0u;
+                v |= byte << (8 * b);
+            }
+            word[i] = v;
+        }
+    }
+    code = 0;
+    inv = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t b = (word[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+        const bool ok = base_valid(b);
+        code |= (ok ? base_code(b) : 0u) << (30 - 2 * i);
+        inv |= (ok ? 0u : 1u) << i;
+    }
+}
+
+// The same 16 bases from the packed layout (base a multiple of 16).
+__device__ __forceinline__ void packed16(const uint32_t* __restrict__ packed,
+                                         const uint32_t* __restrict__ invalid, int64_t base,
+                                         uint64_t n, uint32_t& code, uint32_t& inv) {
+    if (base < 0 || (uint64_t)base >= n) {
+        code = 0;
+        inv = 0xFFFFu;
+        return;
+    }
+    const uint64_t wi = (uint64_t)base >> 4;
+    code = packed[wi];
+    inv = invalid ? (invalid[wi >> 1] >> (16 * (wi & 1))) & 0xFFFFu : 0u;
+    const uint64_t left = n - (uint64_t)base;
+    if (left < 16) {
+        inv |= (0xFFFFu << left) & 0xFFFFu;
+        code &= ~(0xFFFFFFFFu >> (2 * left));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hash.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x ^= x >> 32;
+    x *= 0x9E3779B97F4A7C15ull;
+    x ^= x >> 29;
+    x *= 0x243F6A8885A308D3ull;
+    x ^= x >> 32;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t revpairs32(uint32_t x) {
+    x = __builtin_bitreverse32(x);
+    return ((x >> 1) & 0x55555555u) | ((x & 0x55555555u) << 1);
+}
+__device__ __forceinline__ uint64_t revpairs64(uint64_t x) {
+    x = __builtin_bitreverse64(x);
+    return ((x >> 1) & 0x5555555555555555ull) | ((x & 0x5555555555555555ull) << 1);
+}
+
+// k-mer values (canonical or forward, hashed or not) of the 16 positions of
+// lane t, from the LDS code/invalid words t, t+1, t+2.  bad: bit e set iff the
+// k-mer at position e covers an invalid base.
+template <bool KM64>
+__device__ __forceinline__ void lane_kmers(const uint32_t* s_code, const uint32_t* s_inv, int t,
+                                           uint32_t k, bool canon, bool hashed,
+                                           uint64_t (&val)[kR], uint32_t& bad) {
+    const uint32_t w0 = s_code[t], w1 = s_code[t + 1], w2 = s_code[t + 2];
+    const uint64_t M = (uint64_t)s_inv[t] | ((uint64_t)s_inv[t + 1] << 16) |
+                       ((uint64_t)s_inv[t + 2] << 32);
+    uint64_t A = M;
+    uint32_t len = 1;
+    while (2u * len <= k) {
+        A |= A >> len;
+        len *= 2u;
+    }
+    bad = (uint32_t)((A | (A >> (k - len))) & 0xFFFFu);
+
+    const uint64_t hi = ((uint64_t)w0 << 32) | w1;
+    const uint64_t mid = ((uint64_t)w1 << 32) | w2;
+    // incoming bases k .. k+15 (base k-1+e enters at position e)
+    const uint32_t inW = k < 16u ? (uint32_t)((hi << (2u * k)) >> 32)
+                                 : (uint32_t)((mid << (2u * k - 32u)) >> 32);
+    if (KM64) {
+        const uint64_t mask = (1ull << (2u * k)) - 1ull;
+        uint64_t fwd = hi >> (64u - 2u * k);
+        uint64_t rc = revpairs64(~fwd) >> (64u - 2u * k);
+        const uint32_t sh = 2u * k - 2u;
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            if (e > 0) {
+                const uint32_t c = (inW >> (30 - 2 * (e - 1))) & 3u;
+                fwd = ((fwd << 2) | c) & mask;
+                rc = (rc >> 2) | ((uint64_t)(c ^ 3u) << sh);
+            }
+            const uint64_t cv = (canon && rc < fwd) ? rc : fwd;
+            val[e] = hashed ? mix64(cv) : cv;
+        }
+    } else {
+        const uint32_t mask = k == 16u ? 0xFFFFFFFFu : ((1u << (2u * k)) - 1u);
+        uint32_t fwd = (uint32_t)(hi >> (64u - 2u * k));
+        uint32_t rc = revpairs32(~fwd) >> (32u - 2u * k);
+        const uint32_t sh = 2u * k - 2u;
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            if (e > 0) {
+                const uint32_t c = (inW >> (30 - 2 * (e - 1))) & 3u;
+                fwd = ((fwd << 2) | c) & mask;
+                rc = (rc >> 2) | ((c ^ 3u) << sh);
+            }
+            const uint32_t cv = (canon && rc < fwd) ? rc : fwd;
+            val[e] = hashed ? mix64((uint64_t)cv) : (uint64_t)cv;
+        }
+    }
+}
+
+// Stage the code/invalid words of bases [K0, K0 + 16 * nw) into LDS.
+template <int IN>
+__device__ __forceinline__ void stage_bases(const GenomeInput& in, int64_t K0, int nw,
+                                            uint32_t* s_code, uint32_t* s_inv, int tid, int nt) {
+    for (int i = tid; i < nw; i += nt) {
+        uint32_t code, inv;
+        const int64_t base = K0 + 16 * (int64_t)i;
+        if (IN == kInAscii) ascii16(in.seq, base, in.n, in.aligned != 0, code, inv);
+        else packed16(in.packed, in.invalid, base, in.n, code, inv);
+        s_code[i] = code;
+        s_inv[i] = inv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pack2bit: one lane per 16 bases.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pack2bit_kernel(const uint8_t* __restrict__ seq, uint64_t n,
+                                                       uint32_t* __restrict__ packed,
+                                                       uint32_t* __restrict__ invalid, int aligned,
+                                                       uint64_t nwords) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t code = 0, inv = 0;
+    if (i < nwords) {
+        ascii16(seq, (int64_t)(i * 16), n, aligned != 0, code, inv);
+        const uint64_t left = n - i * 16;
+        if (left < 16) inv &= (1u << left) - 1u;  // bits past n are zero
+        packed[i] = code;
+    }
+    const int lane = lane_id();
+    const uint32_t other = shfl(inv, lane, 1);
+    if (invalid && i < nwords && (i & 1) == 0) invalid[i >> 1] = inv | (other << 16);
+}
+
+// ---------------------------------------------------------------------------
+// kmers: one tile of 16 * NT positions per workgroup.
+// ---------------------------------------------------------------------------
+template <int NT, int IN, bool KM64>
+__global__ __launch_bounds__(NT) void kmers_kernel(GenomeInput in, uint32_t k, uint32_t flags,
+                                                   uint64_t nk, uint64_t* __restrict__ out) {
+    constexpr int P = NT * kR;
+    constexpr int NW = NT + 2;
+    __shared__ uint32_t s_code[NW], s_inv[NW];
+    const int tid = (int)threadIdx.x;
+    const int64_t K0 = (int64_t)blockIdx.x * P;
+    stage_bases<IN>(in, K0, NW, s_code, s_inv, tid, NT);
+    __syncthreads();
+    uint64_t val[kR];
+    uint32_t bad;
+    lane_kmers<KM64>(s_code, s_inv, tid, k, (flags & 1u) == 0u, (flags & 2u) == 0u, val, bad);
+    const uint64_t p = (uint64_t)K0 + (uint64_t)tid * kR;
+#pragma unroll
+    for (int e = 0; e < kR; ++e)
+        if (p + e < nk) out[p + e] = ((bad >> e) & 1u) ? ~0ull : val[e];
+}
+
+// ---------------------------------------------------------------------------
+// Minimizers.
+// ---------------------------------------------------------------------------
+
+// Leftmost minimum of keys.  FULL compares (value, tag) -- needed only when a
+// valid key may carry the all-ones value (hashed k >= 30); otherwise values
+// alone decide, and ties keep the left (earlier) operand.
+template <bool FULL>
+struct OpKeyMin {
+    using T = Key;
+    static __device__ __forceinline__ Key identity() {
+        Key r;
+        r.lo = 0xFFFFFFFFu;
+        r.hi = 0xFFFFFFFFu;
+        r.tag = 0xFFFFu;
+        return r;
+    }
+    static __device__ __forceinline__ bool less(const Key& a, const Key& b) {
+        const uint64_t ha = ((uint64_t)a.hi << 32) | a.lo;
+        const uint64_t hb = ((uint64_t)b.hi << 32) | b.lo;
+        if (FULL) return ha < hb || (ha == hb && a.tag < b.tag);
+        return ha < hb;
+    }
+    static __device__ __forceinline__ Key combine(Key l, Key r) { return less(r, l) ? r : l; }
+};
+
+__device__ __forceinline__ uint32_t pad16(uint32_t i) { return i + (i >> 4); }
+
+// Exclusive prefix of the tile's store count over the tiles before it.
+__device__ uint64_t tile_lookback(uint64_t* status, uint64_t tile, uint64_t total,
+                                  uint32_t* err) {
+    const uint64_t kAgg = 1ull << 62, kInc = 2ull << 62, kVal = (1ull << 62) - 1ull;
+    if (tile == 0) {
+        __hip_atomic_store(&status[0], kInc | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+    }
+    __hip_atomic_store(&status[tile], kAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    uint64_t j = tile - 1;
+    uint32_t spins = 0;
+    for (;;) {
+        const uint64_t s = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t f = s >> 62;
+        if (f == 0) {
+            // Bounded wait: a predecessor that never publishes (which a correct
+            // launch cannot produce) flags an error instead of hanging.
+            if (++spins > (1u << 22)) {
+                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += s & kVal;
+        if (f == 2) break;
+        --j;
+    }
+    __hip_atomic_store(&status[tile], kInc | (excl + total), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+template <int NT, int IN, bool KM64, bool FULL>
+__global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, MinimizerArgs a) {
+    using Op = OpKeyMin<FULL>;
+    constexpr int P = NT * kR;
+    constexpr int NW = NT + 2;
+    constexpr int NWV = NT / kWave;
+    constexpr uint32_t WS = kWave * kR;  // keys per wave
+    __shared__ uint32_t s_code[NW], s_inv[NW];
+    __shared__ uint64_t s_h[P + P / 16];   // prefix minima, later the staged output values
+    __shared__ uint16_t s_tag[P + P / 16]; // their tags, later the staged output positions
+    __shared__ Key s_carryF[NWV], s_carryB[NWV];
+    __shared__ uint32_t s_lastTag[NWV];
+    __shared__ uint32_t s_wsum[NWV];
+    __shared__ uint64_t s_tile, s_excl;
+
+    const int tid = (int)threadIdx.x;
+    const int lane = lane_id();
+    const int wv = tid >> 6;
+    const uint32_t w = a.w;
+
+    if (tid == 0) s_tile = atomicAdd((unsigned long long*)a.counter, 1ull);
+    __syncthreads();
+    const uint64_t tile = s_tile;
+    const int64_t p0 = (int64_t)(tile * a.tw);
+    const int64_t K0 = p0 - 16;
+
+    // 1. bases
+    stage_bases<IN>(in, K0, NW, s_code, s_inv, tid, NT);
+    __syncthreads();
+
+    // 2. keys
+    Key pf[kR], sf[kR];
+    {
+        uint64_t val[kR];
+        uint32_t bad;
+        lane_kmers<KM64>(s_code, s_inv, tid, a.k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u, val,
+                         bad);
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const uint32_t j = (uint32_t)tid * kR + e;
+            const bool inv = (bad >> e) & 1u;
+            pf[e].lo = inv ? 0xFFFFFFFFu : (uint32_t)val[e];
+            pf[e].hi = inv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
+            pf[e].tag = j | (inv ? kInvalidTag : 0u);
+            sf[e] = pf[e];
+        }
+    }
+
+    // 3. sliding minimum: in-segment prefix/suffix minima, segments of w keys
+    //    aligned to multiples of w inside the tile
+    const uint32_t span = (w + kR - 1) / kR;
+    const uint32_t m0 = ((uint32_t)tid * kR) % w;
+    slab_prefix<Op, kR>(pf, m0, w, span, lane, Op::identity());
+    slab_suffix<Op, kR>(sf, m0, w, span, lane);
+    if (lane == kWave - 1) s_carryF[wv] = pf[kR - 1];
+    if (lane == 0) s_carryB[wv] = sf[0];
+#pragma unroll
+    for (int e = 0; e < kR; ++e) {
+        const uint32_t j = (uint32_t)tid * kR + e;
+        s_h[pad16(j)] = ((uint64_t)pf[e].hi << 32) | pf[e].lo;
+        s_tag[pad16(j)] = (uint16_t)pf[e].tag;
+    }
+    __syncthreads();
+    // the wave's last segment continues into the next wave (w <= keys per wave)
+    if (wv < NWV - 1) {
+        const uint32_t wend = (uint32_t)(wv + 1) * WS;
+        const uint32_t last = (wend - 1u) % w;
+        if (last != w - 1u) {
+            const Key c = s_carryB[wv + 1];
+            const uint32_t head = wend - 1u - last;
+#pragma unroll
+            for (int e = 0; e < kR; ++e)
+                if ((uint32_t)tid * kR + e >= head) sf[e] = Op::combine(sf[e], c);
+        }
+    }
+    uint32_t mtag[kR];
+    {
+        uint32_t m = m0;
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const uint32_t j = (uint32_t)tid * kR + e;
+            const uint32_t q = j + w - 1u;
+            Key r;
+            if (q < (uint32_t)P) {
+                const uint64_t h = s_h[pad16(q)];
+                r.lo = (uint32_t)h;
+                r.hi = (uint32_t)(h >> 32);
+                r.tag = s_tag[pad16(q)];
+                // prefix minima of a segment that started in the previous wave
+                const uint32_t qw = q / WS;
+                if (qw > 0) {
+                    const uint32_t ws0 = qw * WS;
+                    const uint32_t rem = ws0 % w;
+                    const uint32_t first_head = rem == 0u ? ws0 : ws0 + (w - rem);
+                    if (q < first_head) r = Op::combine(s_carryF[qw - 1], r);
+                }
+                if (m != 0u) r = Op::combine(sf[e], r);
+            } else {
+                r = Op::identity();
+            }
+            // keep the key itself (value in sf) for the output stage
+            sf[e] = r;
+            mtag[e] = r.tag;
+            m = (m + 1u == w) ? 0u : m + 1u;
+        }
+    }
+    if (lane == kWave - 1) s_lastTag[wv] = mtag[kR - 1];
+    __syncthreads();
+
+    // 4. dedup: store window p iff it has a minimizer at a new position
+    uint32_t emit = 0;
+    {
+        uint32_t prev = shfl(mtag[kR - 1], lane, -1);
+        if (lane == 0) prev = wv > 0 ? s_lastTag[wv - 1] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const uint32_t j = (uint32_t)tid * kR + e;
+            const int64_t p = K0 + (int64_t)j;
+            const bool owned = j >= 16u && j < 16u + a.tw && p < (int64_t)a.nwin;
+            const bool valid = (mtag[e] & kInvalidTag) == 0u;
+            const bool fresh = p == 0 || mtag[e] != prev;
+            emit |= (owned && valid && fresh ? 1u : 0u) << e;
+            prev = mtag[e];
+        }
+    }
+
+    // 5. ordered compaction
+    const uint32_t cnt = (uint32_t)__builtin_popcount(emit);
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = shfl(incl, lane, -d);
+        if (lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) s_wsum[wv] = incl;
+    __syncthreads();  // also: every read of s_h / s_tag above is complete
+    uint32_t wbase = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < NWV; ++i) {
+        const uint32_t v = s_wsum[i];
+        wbase += i < wv ? v : 0u;
+        total += v;
+    }
+    uint32_t slot = wbase + incl - cnt;
+#pragma unroll
+    for (int e = 0; e < kR; ++e) {
+        if ((emit >> e) & 1u) {
+            s_h[slot] = ((uint64_t)sf[e].hi << 32) | sf[e].lo;
+            s_tag[slot] = (uint16_t)(sf[e].tag & 0x7FFFu);
+            ++slot;
+        }
+    }
+    if (tid == 0) s_excl = tile_lookback(a.status, tile, total, a.err);
+    __syncthreads();
+    const uint64_t excl = s_excl;
+    for (uint32_t i = (uint32_t)tid; i < total; i += NT) {
+        const uint64_t g = excl + i;
+        if (g < a.capacity) {
+            a.out_hash[g] = s_h[i];
+            a.out_pos[g] = (uint32_t)(K0 + (int64_t)s_tag[i]);
+        }
+    }
+    if (tid == 0 && tile == a.ntiles - 1) *a.d_count = excl + total;
+}
+
+__global__ void zero_words_kernel(uint64_t* __restrict__ p, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+int launch_zero(uint64_t* p, uint64_t words, hipStream_t s) {
+    const uint64_t blocks = (words + 255) / 256 < 1024 ? (words + 255) / 256 : 1024;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)(blocks ? blocks : 1)), dim3(256), 0, s, p,
+                       words);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_pack2bit(const uint8_t* seq, uint64_t n, uint32_t* packed, uint32_t* invalid,
+                    hipStream_t s) {
+    const uint64_t nwords = (n + 15) / 16;
+    // one extra lane when nwords is odd so the pair (i, i+1) always exists
+    const uint64_t lanes = (nwords + 1) & ~1ull;
+    const uint64_t blocks = (lanes + 255) / 256;
+    const int aligned = ((uintptr_t)seq & 15u) == 0;
+    hipLaunchKernelGGL(pack2bit_kernel, dim3((unsigned)blocks), dim3(256), 0, s, seq, n, packed,
+                       invalid, aligned, nwords);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_kmers(const GenomeInput& in, uint32_t k, uint32_t flags, uint64_t* out, hipStream_t s) {
+    constexpr int NT = 256;
+    const uint64_t nk = in.n - k + 1;
+    const uint64_t blocks = (nk + NT * kR - 1) / (NT * kR);
+    if (k <= 16) {
+        if (in.kind == kInAscii)
+            hipLaunchKernelGGL((kmers_kernel<NT, kInAscii, false>), dim3((unsigned)blocks), dim3(NT), 0, s, in, k, flags, nk, out);
+        else
+            hipLaunchKernelGGL((kmers_kernel<NT, kIn2bit, false>), dim3((unsigned)blocks), dim3(NT), 0, s, in, k, flags, nk, out);
+    } else {
+        if (in.kind == kInAscii)
+            hipLaunchKernelGGL((kmers_kernel<NT, kInAscii, true>), dim3((unsigned)blocks), dim3(NT), 0, s, in, k, flags, nk, out);
+        else
+            hipLaunchKernelGGL((kmers_kernel<NT, kIn2bit, true>), dim3((unsigned)blocks), dim3(NT), 0, s, in, k, flags, nk, out);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+uint32_t minimizer_tile_windows(uint32_t nt, uint32_t w) {
+    const uint32_t P = nt * kR;
+    if (P < 32u + w) return 0;
+    return (P - 16u - (w - 1u)) & ~15u;
+}
+
+uint64_t minimizer_workspace_bytes(uint64_t ntiles) { return kWsStatusOffset + 8ull * ntiles; }
+
+template <int NT, int IN>
+static void launch_min_nt(const GenomeInput& in, const MinimizerArgs& a, bool km64, bool full,
+                          hipStream_t s) {
+    const dim3 grid((unsigned)a.ntiles), block(NT);
+    if (!km64)
+        hipLaunchKernelGGL((minimizer_kernel<NT, IN, false, false>), grid, block, 0, s, in, a);
+    else if (!full)
+        hipLaunchKernelGGL((minimizer_kernel<NT, IN, true, false>), grid, block, 0, s, in, a);
+    else
+        hipLaunchKernelGGL((minimizer_kernel<NT, IN, true, true>), grid, block, 0, s, in, a);
+}
+
+int launch_minimizers(const GenomeInput& in, MinimizerArgs a, uint32_t nt, void* workspace,
+                      hipStream_t s) {
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    a.counter = reinterpret_cast<uint64_t*>(ws);
+    a.err = reinterpret_cast<uint32_t*>(ws + 8);
+    a.status = reinterpret_cast<uint64_t*>(ws + kWsStatusOffset);
+    if (launch_zero(reinterpret_cast<uint64_t*>(ws), kWsStatusOffset / 8 + a.ntiles, s) != 0)
+        return -1;
+    const bool km64 = a.k > 16;
+    const bool full = a.k >= 30 && (a.flags & 2u) == 0u;
+    if (in.kind == kInAscii) {
+        if (nt == 128) launch_min_nt<128, kInAscii>(in, a, km64, full, s);
+        else if (nt == 512) launch_min_nt<512, kInAscii>(in, a, km64, full, s);
+        else launch_min_nt<256, kInAscii>(in, a, km64, full, s);
+    } else {
+        if (nt == 128) launch_min_nt<128, kIn2bit>(in, a, km64, full, s);
+        else if (nt == 512) launch_min_nt<512, kIn2bit>(in, a, km64, full, s);
+        else launch_min_nt<256, kIn2bit>(in, a, km64, full, s);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace sws

@@ -1,0 +1,240 @@
+// sliding.hip -- sliding window sums y_i = x_i (+) ... (+) x_{i+w-1}
+// (Sec. 2.2, Eq. 2) on gfx950.
+//
+// Generic path (any associative operator; Sec. 3.1, Alg. 2 with the vector
+// length taken equal to w).  Cut the index space into segments of w elements
+// starting at multiples of w.  With Pf the in-segment prefix and Sf the
+// in-segment suffix,
+//     y_i = Pf_{i+w-1}                 if i starts a segment,
+//     y_i = Sf_i (+) Pf_{i+w-1}        otherwise,
+// since the window [i, i+w-1] is the tail of i's segment followed by the head
+// of the next one.  That is three operator applications per output whatever w
+// is; only associativity is used and the left operand is always the earlier
+// element, so non-commutative operators keep the order of Eq. 2.
+//
+// Mapping: every wavefront streams its own contiguous run of "slabs" of
+// S = 64*R elements; lane l holds elements [l*R, l*R+R) of a slab in
+// registers.  Prefix and suffix sums are serial inside a lane; across lanes a
+// segmented Hillis-Steele scan with log2(ceil(w/R)) shuffle steps carries the
+// partial sums of segments that span lanes (w <= S, so a segment spans at most
+// two slabs).  Across slabs the carried state is one value each way: the
+// prefix at the end of the previous slab (the paper's vector Y of Alg. 2) and
+// the suffix at the start of the next slab, which patches the last segment
+// of the current slab.  Prefix sums of two consecutive slabs sit in a per-wave
+// LDS ring, from which each lane reads Pf_{i+w-1}.  No workgroup barrier, no
+// global scratch; HBM sees each element read once and each output written once.
+//
+// Log path (MIN and MAX only; Sec. 3.1, the commutative case).  With
+// m^(1) = x, m^(2s)_i = m^(s)_i (+) m^(s)_{i+s} and 2^t the largest power of two
+// not above w, y_i = m^(2^t)_i (+) m^(2^t)_{i+w-2^t}; the two halves overlap,
+// which idempotence allows.  floor(log2 w) + 1 applications per output.  A
+// workgroup loads a tile plus its (w-1)-element halo into LDS and runs the
+// doubling levels between two LDS buffers.
+#include "sws_device.hpp"
+#include "sws_internal.hpp"
+#include "sws_scan.hpp"
+
+namespace sws {
+
+// ---------------------------------------------------------------------------
+// Generic path.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ring_index(uint32_t r) { return r + (r >> 4); }
+
+template <class Op, int R, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
+    const typename Op::T* __restrict__ x, uint64_t n, uint32_t w, typename Op::T* __restrict__ y,
+    uint64_t count, uint64_t total_slabs, uint64_t slabs_per_wave, int vec) {
+    using T = typename Op::T;
+    constexpr uint32_t S = kWave * R;
+    constexpr uint32_t RING = 2 * S;
+    __shared__ T ring_all[WAVES][RING + RING / 16];
+    const int lane = lane_id();
+    const int wv = (int)(threadIdx.x >> 6);
+    T* ring = ring_all[wv];
+    const uint64_t gw = (uint64_t)blockIdx.x * WAVES + (uint64_t)wv;
+    const uint64_t s0 = gw * slabs_per_wave;
+    if (s0 >= total_slabs) return;
+    const uint64_t s1 = s0 + slabs_per_wave < total_slabs ? s0 + slabs_per_wave : total_slabs;
+
+    const uint32_t span = (w + R - 1) / R;
+    const uint32_t lane_mod = (uint32_t)((uint32_t)(lane * R) % w);
+    const uint32_t slab_mod_step = S % w;
+    const T ident = Op::identity();
+
+    // state of slab A = s0
+    uint32_t mA = (uint32_t)((s0 * (uint64_t)S) % w);
+    T sfA[R];
+    T carryA;
+    {
+        T v[R];
+        load_run<T, R>(x, n, s0 * S + (uint64_t)lane * R, vec != 0, ident, v);
+        uint32_t m0 = mA + lane_mod;
+        m0 = m0 >= w ? m0 - w : m0;
+#pragma unroll
+        for (int e = 0; e < R; ++e) sfA[e] = v[e];
+        slab_prefix<Op, R>(v, m0, w, span, lane, ident);
+#pragma unroll
+        for (int e = 0; e < R; ++e) ring[ring_index((uint32_t)lane * R + e)] = v[e];
+        carryA = lane_value(v[R - 1], kWave - 1);
+        slab_suffix<Op, R>(sfA, m0, w, span, lane);
+    }
+    uint32_t half = 0;  // ring half holding slab A's prefix sums
+
+    for (uint64_t s = s0; s < s1; ++s) {
+        const uint64_t baseA = s * S;
+        uint32_t mB = mA + slab_mod_step;
+        mB = mB >= w ? mB - w : mB;
+        // slab B = s + 1: prefix sums into the other ring half, suffix sums kept
+        T sfB[R];
+        {
+            T v[R];
+            load_run<T, R>(x, n, baseA + S + (uint64_t)lane * R, vec != 0, ident, v);
+            uint32_t m0 = mB + lane_mod;
+            m0 = m0 >= w ? m0 - w : m0;
+#pragma unroll
+            for (int e = 0; e < R; ++e) sfB[e] = v[e];
+            slab_prefix<Op, R>(v, m0, w, span, lane, carryA);
+            const uint32_t off = (half ^ 1u) * S;
+#pragma unroll
+            for (int e = 0; e < R; ++e) ring[ring_index(off + (uint32_t)lane * R + e)] = v[e];
+            carryA = lane_value(v[R - 1], kWave - 1);
+            slab_suffix<Op, R>(sfB, m0, w, span, lane);
+        }
+        // the last segment of A continues into B: append B's leading suffix
+        {
+            const T c = lane_value(sfB[0], 0);
+            const uint32_t last = (mA + S - 1u) % w;
+            if (last != w - 1u) {
+                const uint32_t head_rel = S - 1u - last;
+#pragma unroll
+                for (int e = 0; e < R; ++e)
+                    if ((uint32_t)lane * R + e >= head_rel) sfA[e] = Op::combine(sfA[e], c);
+            }
+        }
+        wave_lds_sync();
+        // outputs of slab A
+        {
+            T out[R];
+            uint32_t m = mA + lane_mod;
+            m = m >= w ? m - w : m;
+            const uint32_t aoff = half * S;
+#pragma unroll
+            for (int e = 0; e < R; ++e) {
+                const uint32_t r = (aoff + (uint32_t)lane * R + e + w - 1u) & (RING - 1u);
+                const T pf = ring[ring_index(r)];
+                out[e] = (m == 0u) ? pf : Op::combine(sfA[e], pf);
+                m = (m + 1u == w) ? 0u : m + 1u;
+            }
+            store_run<T, R>(y, count, baseA + (uint64_t)lane * R, vec != 0, out);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int e = 0; e < R; ++e) sfA[e] = sfB[e];
+        mA = mB;
+        half ^= 1u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Log path (MIN / MAX).
+// ---------------------------------------------------------------------------
+template <class Op, int NT>
+__global__ __launch_bounds__(NT) void sliding_log_kernel(const uint32_t* __restrict__ x, uint64_t n,
+                                                         uint32_t w, uint32_t* __restrict__ y,
+                                                         uint64_t count, uint32_t tile) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t L = tile + w - 1u;
+    uint32_t* bufA = lds;
+    uint32_t* bufB = lds + L;
+    const uint64_t t0 = (uint64_t)blockIdx.x * tile;
+    for (uint32_t i = threadIdx.x; i < L; i += NT) {
+        const uint64_t g = t0 + i;
+        bufA[i] = g < n ? x[g] : Op::identity();
+    }
+    __syncthreads();
+    uint32_t p2 = 1;
+    while (p2 * 2u <= w) p2 *= 2u;
+    uint32_t* src = bufA;
+    uint32_t* dst = bufB;
+    for (uint32_t s = 1; s < p2; s *= 2u) {
+        // windows of 2s: positions [0, L - 2s + 1)
+        const uint32_t len = L - 2u * s + 1u;
+        for (uint32_t i = threadIdx.x; i < len; i += NT) dst[i] = Op::combine(src[i], src[i + s]);
+        __syncthreads();
+        uint32_t* t = src;
+        src = dst;
+        dst = t;
+    }
+    const uint32_t shift = w - p2;
+    for (uint32_t i = threadIdx.x; i < tile; i += NT) {
+        const uint64_t g = t0 + i;
+        if (g < count) y[g] = Op::combine(src[i], src[i + shift]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <class Op, int R, int WAVES>
+static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
+                          hipStream_t s) {
+    using T = typename Op::T;
+    constexpr uint64_t S = kWave * R;
+    const uint64_t total_slabs = (count + S - 1) / S;
+    // aim for about 8 waves per SIMD-slot-round: 256 CUs x 32 waves
+    const uint64_t target_waves = 256ull * 32ull;
+    uint64_t spw = (total_slabs + target_waves - 1) / target_waves;
+    if (spw < 1) spw = 1;
+    const uint64_t waves = (total_slabs + spw - 1) / spw;
+    const uint64_t blocks = (waves + WAVES - 1) / WAVES;
+    const int vec = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0 ? 1 : 0;
+    hipLaunchKernelGGL((sliding_generic_kernel<Op, R, WAVES>), dim3((unsigned)blocks),
+                       dim3(WAVES * kWave), 0, s, static_cast<const T*>(x), n, w,
+                       static_cast<T*>(y), count, total_slabs, spw, vec);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <class Op>
+static int launch_log(const void* x, uint64_t n, uint32_t w, void* y, uint64_t count, hipStream_t s) {
+    constexpr int NT = 256;
+    const uint32_t tile = 4096;
+    const size_t lds = 2ull * (tile + w - 1ull) * sizeof(uint32_t);
+    const uint64_t blocks = (count + tile - 1) / tile;
+    hipLaunchKernelGGL((sliding_log_kernel<Op, NT>), dim3((unsigned)blocks), dim3(NT), lds, s,
+                       static_cast<const uint32_t*>(x), n, w, static_cast<uint32_t*>(y), count, tile);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Windows up to 64*16 elements use 16 elements per lane; up to 64*32, 32.
+uint32_t generic_max_window() { return kWave * 32; }
+
+// A tile of 4096 outputs plus a halo of w-1 in two LDS buffers stays within 64 KB.
+uint32_t log_max_window() { return 4096; }
+
+int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
+                           hipStream_t s) {
+    const bool big = w > (uint32_t)(kWave * 16);
+    switch (op) {
+    case kOpAdd: return big ? launch_generic<OpAdd, 32, 2>(x, n, w, y, count, s)
+                            : launch_generic<OpAdd, 16, 4>(x, n, w, y, count, s);
+    case kOpMin: return big ? launch_generic<OpMin, 32, 2>(x, n, w, y, count, s)
+                            : launch_generic<OpMin, 16, 4>(x, n, w, y, count, s);
+    case kOpMax: return big ? launch_generic<OpMax, 32, 2>(x, n, w, y, count, s)
+                            : launch_generic<OpMax, 16, 4>(x, n, w, y, count, s);
+    case kOpAffine: return big ? launch_generic<OpAffine, 32, 1>(x, n, w, y, count, s)
+                               : launch_generic<OpAffine, 16, 4>(x, n, w, y, count, s);
+    default: return -2;
+    }
+}
+
+int launch_sliding_log(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
+                       hipStream_t s) {
+    switch (op) {
+    case kOpMin: return launch_log<OpMin>(x, n, w, y, count, s);
+    case kOpMax: return launch_log<OpMax>(x, n, w, y, count, s);
+    default: return -2;
+    }
+}
+
+}  // namespace sws

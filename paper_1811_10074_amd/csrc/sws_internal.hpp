@@ -1,0 +1,55 @@
+// sws_internal.hpp -- declarations shared by the libsws host entry points and
+// the kernel translation units (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sws {
+
+enum { kOpAdd = 0, kOpMin = 1, kOpMax = 2, kOpAffine = 3 };
+
+// sliding.hip
+uint32_t generic_max_window();
+uint32_t log_max_window();
+int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
+                           hipStream_t s);
+int launch_sliding_log(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
+                       hipStream_t s);
+
+// genome.hip
+enum { kInAscii = 0, kIn2bit = 1 };
+constexpr uint64_t kWsStatusOffset = 256;  // workspace: counter, error flag, then tile status
+
+struct GenomeInput {
+    int kind;                 // kInAscii or kIn2bit
+    int aligned;              // seq is 16-byte aligned
+    const uint8_t* seq;       // ASCII bases
+    const uint32_t* packed;   // 2-bit words
+    const uint32_t* invalid;  // invalid bits, may be null
+    uint64_t n;
+};
+
+struct MinimizerArgs {
+    uint32_t k, w, flags, tw;       // tw: windows stored per tile
+    uint64_t nwin;                  // windows in the sequence
+    uint64_t ntiles;
+    uint64_t* out_hash;
+    uint32_t* out_pos;
+    uint64_t capacity;
+    uint64_t* d_count;
+    uint64_t* counter;              // workspace
+    uint32_t* err;
+    uint64_t* status;
+};
+
+int launch_zero(uint64_t* p, uint64_t words, hipStream_t s);
+int launch_pack2bit(const uint8_t* seq, uint64_t n, uint32_t* packed, uint32_t* invalid,
+                    hipStream_t s);
+int launch_kmers(const GenomeInput& in, uint32_t k, uint32_t flags, uint64_t* out, hipStream_t s);
+uint32_t minimizer_tile_windows(uint32_t nt, uint32_t w);
+uint64_t minimizer_workspace_bytes(uint64_t ntiles);
+int launch_minimizers(const GenomeInput& in, MinimizerArgs a, uint32_t nt, void* workspace,
+                      hipStream_t s);
+
+}  // namespace sws

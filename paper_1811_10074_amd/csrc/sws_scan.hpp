@@ -1,0 +1,127 @@
+// sws_scan.hpp -- per-wavefront segmented prefix/suffix scans and vector
+// loads/stores of "runs" (R consecutive elements per lane), shared by the
+// sliding-sum and minimizer kernels.
+//
+// Segments of length w start at every index that is a multiple of w.  A lane
+// holds R consecutive elements; m0 is the first one's index mod w.  The scans
+// are exact for any associative operator: combine(l, r) always receives the
+// earlier operand on the left.
+#pragma once
+
+#include "sws_device.hpp"
+
+namespace sws {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T, int R>
+__device__ __forceinline__ void load_run(const T* __restrict__ x, uint64_t n, uint64_t p, bool vec,
+                                         T identity, T (&v)[R]) {
+    constexpr int kVec = (int)(R * sizeof(T) / 16);
+    if (vec && p + R <= n) {
+        const u32x4* src = reinterpret_cast<const u32x4*>(x + p);
+        u32x4 q[kVec];
+#pragma unroll
+        for (int i = 0; i < kVec; ++i) q[i] = __builtin_nontemporal_load(src + i);
+        const T* t = reinterpret_cast<const T*>(q);
+#pragma unroll
+        for (int e = 0; e < R; ++e) v[e] = t[e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < R; ++e) v[e] = (p + e < n) ? x[p + e] : identity;
+    }
+}
+
+template <class T, int R>
+__device__ __forceinline__ void store_run(T* __restrict__ y, uint64_t limit, uint64_t p, bool vec,
+                                          const T (&v)[R]) {
+    constexpr int kVec = (int)(R * sizeof(T) / 16);
+    if (vec && p + R <= limit) {
+        u32x4* dst = reinterpret_cast<u32x4*>(y + p);
+        const u32x4* q = reinterpret_cast<const u32x4*>(v);
+#pragma unroll
+        for (int i = 0; i < kVec; ++i) __builtin_nontemporal_store(q[i], dst + i);
+    } else {
+#pragma unroll
+        for (int e = 0; e < R; ++e)
+            if (p + e < limit) y[p + e] = v[e];
+    }
+}
+
+// In-segment prefix sums of one slab.  m0 = (position of the lane's first
+// element) mod w.  carry = prefix at the last element of the previous slab.
+template <class Op, int R>
+__device__ __forceinline__ void slab_prefix(typename Op::T (&v)[R], uint32_t m0, uint32_t w,
+                                            uint32_t span, int lane, typename Op::T carry) {
+    using T = typename Op::T;
+    uint32_t headmask = 0;
+    {
+        uint32_t m = m0;
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+            headmask |= (m == 0u ? 1u : 0u) << e;
+            m = (m + 1u == w) ? 0u : m + 1u;
+        }
+    }
+#pragma unroll
+    for (int e = 1; e < R; ++e)
+        if (!((headmask >> e) & 1u)) v[e] = Op::combine(v[e - 1], v[e]);
+    // segmented inclusive scan of (has head, value) across lanes
+    uint32_t F = headmask != 0u;
+    T V = v[R - 1];
+    for (uint32_t d = 1; d < span; d <<= 1) {
+        const uint32_t Fo = shfl(F, lane, -(int)d);
+        const T Vo = shfl(V, lane, -(int)d);
+        if (lane >= (int)d && !F) {
+            V = Op::combine(Vo, V);
+            F = Fo;
+        }
+    }
+    const uint32_t Fe = shfl(F, lane, -1);
+    const T Ve = shfl(V, lane, -1);
+    T c = carry;
+    if (lane > 0) c = Fe ? Ve : Op::combine(carry, Ve);
+    // elements before the lane's first head extend the carried segment
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+        if ((headmask & ((2u << e) - 1u)) == 0u) v[e] = Op::combine(c, v[e]);
+}
+
+// In-segment suffix sums of one slab, without the part of the last segment
+// that lies in the next slab (patched by the caller).
+template <class Op, int R>
+__device__ __forceinline__ void slab_suffix(typename Op::T (&v)[R], uint32_t m0, uint32_t w,
+                                            uint32_t span, int lane) {
+    using T = typename Op::T;
+    uint32_t endmask = 0;
+    {
+        uint32_t m = m0;
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+            endmask |= (m + 1u == w ? 1u : 0u) << e;
+            m = (m + 1u == w) ? 0u : m + 1u;
+        }
+    }
+#pragma unroll
+    for (int e = R - 2; e >= 0; --e)
+        if (!((endmask >> e) & 1u)) v[e] = Op::combine(v[e], v[e + 1]);
+    uint32_t G = endmask != 0u;
+    T U = v[0];
+    for (uint32_t d = 1; d < span; d <<= 1) {
+        const uint32_t Go = shfl(G, lane, (int)d);
+        const T Uo = shfl(U, lane, (int)d);
+        if (lane + (int)d < kWave && !G) {
+            U = Op::combine(U, Uo);
+            G = Go;
+        }
+    }
+    const T Ue = shfl(U, lane, 1);
+    if (lane < kWave - 1) {
+        // elements after the lane's last segment end continue into lane+1
+#pragma unroll
+        for (int e = 0; e < R; ++e)
+            if ((endmask >> e) == 0u) v[e] = Op::combine(v[e], Ue);
+    }
+}
+
+}  // namespace sws

@@ -1,0 +1,83 @@
+"""The C-ABI library: it loads, exports every function the header declares,
+and validates arguments on the host before anything is enqueued (these calls
+return before any device call, so they run without a GPU)."""
+import ctypes
+
+import pytest
+
+from paper_1811_10074_amd import _lib
+
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+NULL = ctypes.c_void_p(0)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_header_function(lib):
+    names = _lib.header_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib._SIGNATURES, name
+
+
+def test_version_and_status(lib):
+    assert lib.sws_abi_version() == 1
+    for st in (0, -1, -2, -3, -4, -5):
+        assert lib.sws_status_str(st)
+    assert b"unknown" in lib.sws_status_str(7)
+
+
+def test_sliding_validation(lib):
+    s = NULL
+    assert lib.sws_sliding_sum(9, 4, FAKE, 100, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_sliding_sum(0, 0, FAKE, 100, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_sliding_sum_ex(0, 4, FAKE, 100, FAKE, 2, s) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_sliding_sum_ex(3, 4, FAKE, 100, FAKE, 2, s) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_sliding_sum_ex(1, 4, FAKE, 100, FAKE, 7, s) == _lib.SWS_ERR_INVALID
+    # n < w: no outputs, not an error, nothing touched
+    assert lib.sws_sliding_sum(0, 10, NULL, 5, NULL, s) == _lib.SWS_OK
+    assert lib.sws_sliding_sum(0, 3, NULL, 5, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_sliding_sum(0, 3, ctypes.c_void_p(0x10002), 5, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_sliding_sum(3, 3, ctypes.c_void_p(0x10004), 5, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_sliding_sum(0, 1 << 20, FAKE, 1 << 21, FAKE, s) == _lib.SWS_ERR_UNSUPPORTED
+
+
+def test_kmer_validation(lib):
+    s = NULL
+    assert lib.sws_kmers(FAKE, 100, 0, 0, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_kmers(FAKE, 100, 32, 0, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_kmers(FAKE, 100, 15, 8, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_kmers(FAKE, 100, 30, 0, FAKE, s) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_kmers(NULL, 10, 15, 0, NULL, s) == _lib.SWS_OK      # n < k
+    assert lib.sws_kmers(NULL, 100, 15, 0, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_pack2bit(NULL, 0, NULL, NULL, s) == _lib.SWS_OK
+    assert lib.sws_pack2bit(NULL, 10, FAKE, NULL, s) == _lib.SWS_ERR_INVALID
+
+
+def test_minimizer_validation(lib):
+    s = NULL
+    b = ctypes.c_uint64(0)
+    assert lib.sws_minimizers_workspace(1 << 26, 15, 10, ctypes.byref(b)) == _lib.SWS_OK
+    ws = b.value
+    assert ws >= 256 + 8 * ((1 << 26) // 2048)
+    assert lib.sws_minimizers_workspace(100, 0, 10, ctypes.byref(b)) == _lib.SWS_ERR_INVALID
+    assert lib.sws_minimizers_workspace(100, 15, 0, ctypes.byref(b)) == _lib.SWS_ERR_INVALID
+    assert lib.sws_minimizers_workspace(100, 15, 2000, ctypes.byref(b)) == _lib.SWS_ERR_UNSUPPORTED
+    n = 1000
+    bound = n - 15 - 10 + 2
+    args = lambda cap, wsb, wsp=FAKE, cnt=FAKE, fl=0: (FAKE, n, 15, 10, fl, FAKE, FAKE, cap, cnt, wsp, wsb, s)
+    assert lib.sws_minimizers(*args(bound - 1, 1 << 20)) == _lib.SWS_ERR_CAPACITY
+    assert lib.sws_minimizers(*args(bound, 16)) == _lib.SWS_ERR_WORKSPACE
+    assert lib.sws_minimizers(*args(bound, 1 << 20, wsp=NULL)) == _lib.SWS_ERR_WORKSPACE
+    assert lib.sws_minimizers(*args(bound, 1 << 20, wsp=ctypes.c_void_p(0x10004))) == _lib.SWS_ERR_WORKSPACE
+    assert lib.sws_minimizers(*args(bound, 1 << 20, cnt=NULL)) == _lib.SWS_ERR_INVALID
+    assert lib.sws_minimizers(*args(bound, 1 << 20, fl=4)) == _lib.SWS_ERR_INVALID
+    assert lib.sws_minimizers(NULL, n, 15, 10, 0, FAKE, FAKE, bound, FAKE, FAKE, 1 << 20, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_minimizers(FAKE, 1 << 32, 15, 10, 0, FAKE, FAKE, 1 << 33, FAKE, FAKE, 1 << 30, s) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_minimizers_2bit(ctypes.c_void_p(0x10002), NULL, n, 15, 10, 0, FAKE, FAKE, bound, FAKE, FAKE, 1 << 20, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_set_minimizer_block(0, 100) == _lib.SWS_ERR_INVALID
+    assert lib.sws_set_minimizer_block(3, 256) == _lib.SWS_ERR_INVALID

@@ -1,0 +1,174 @@
+"""Parity of the HIP packing, k-mer and minimizer kernels with the CPU oracle
+(Sec. 2.4, Fig. 2).  Everything is integer work: bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle_pins
+from gpu_util import dev, host_u32, host_u64, torch_cuda
+from paper_1811_10074_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TILE = 256 * 16  # key positions per minimizer tile (256 threads)
+
+
+def seq_dev(torch, s):
+    if isinstance(s, str):
+        s = np.frombuffer(s.encode(), dtype=np.uint8)
+    return dev(np.ascontiguousarray(s, dtype=np.uint8), torch)
+
+
+def gpu_minimizers(torch, s, k, w, canonical=True, hashed=True):
+    import paper_1811_10074_amd as sws
+    h, p = sws.minimizers(seq_dev(torch, s), k, w, canonical=canonical, hashed=hashed)
+    torch.cuda.synchronize()
+    return host_u64(h), host_u32(p)
+
+
+def assert_same_minimizers(torch, s, k, w, canonical=True, hashed=True, tag=""):
+    gh, gp = gpu_minimizers(torch, s, k, w, canonical, hashed)
+    eh, ep = oracle.minimizers(s, k, w, canonical, hashed)
+    if not (np.array_equal(gp, ep) and np.array_equal(gh, eh)):
+        m = min(len(gp), len(ep))
+        d = np.nonzero((gp[:m] != ep[:m]) | (gh[:m] != eh[:m]))[0]
+        first = int(d[0]) if d.size else m
+        raise AssertionError("%s k=%d w=%d can=%s hash=%s n=%d: gpu %d vs oracle %d, first diff at %d"
+                             % (tag, k, w, canonical, hashed, len(s), len(gp), len(ep), first))
+
+
+def test_pack2bit_layout():
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    for n in (1, 15, 16, 17, 31, 32, 33, 1000, 65_537):
+        s = inputs.dna(n, seed=n, n_rate=0.05, lowercase_rate=0.1)
+        packed, invalid = sws.pack2bit(seq_dev(torch, s))
+        torch.cuda.synchronize()
+        pk, iv = host_u32(packed), host_u32(invalid)
+        lib = oracle.load()
+        codes = np.array([lib.oracle_base_code(int(b)) for b in s], dtype=np.int64)
+        i = np.arange(n)
+        got_code = (pk[i // 16] >> (30 - 2 * (i % 16)).astype(np.uint32)) & 3
+        got_inv = (iv[i // 32] >> (i % 32).astype(np.uint32)) & 1
+        assert np.array_equal(got_inv, (codes < 0).astype(np.uint32)), n
+        assert np.array_equal(got_code, np.where(codes < 0, 0, codes).astype(np.uint32)), n
+        # bits past n are zero
+        tail = np.arange(n, len(pk) * 16)
+        assert np.all(((pk[tail // 16] >> (30 - 2 * (tail % 16)).astype(np.uint32)) & 3) == 0)
+        tail = np.arange(n, len(iv) * 32)
+        assert np.all(((iv[tail // 32] >> (tail % 32).astype(np.uint32)) & 1) == 0)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 15, 16, 17, 19, 21, 29, 30, 31])
+def test_kmers(k):
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    for n in (k, k + 1, 100, TILE + 17, 3 * TILE + 5):
+        s = inputs.dna(n, seed=1000 + n + k, n_rate=0.02, lowercase_rate=0.05)
+        for can in (True, False):
+            for hsh in (True, False):
+                if hsh and k >= 30:
+                    continue
+                got = host_u64(sws.kmers(seq_dev(torch, s), k, canonical=can, hashed=hsh))
+                torch.cuda.synchronize()
+                exp = oracle.kmers(s, k, canonical=can, hashed=hsh)
+                assert np.array_equal(got, exp), (k, n, can, hsh)
+    with pytest.raises(ValueError):
+        sws.kmers(seq_dev(torch, "ACGT" * 20), 30, hashed=True)
+
+
+def test_fig2_worked_example():
+    torch = torch_cuda()
+    g = oracle_pins.read_golden("fig2_worked_example.txt")
+    k, w, s = int(g["k"][0]), int(g["w"][0]), g["sequence"][0]
+    gh, gp = gpu_minimizers(torch, s, k, w, canonical=False, hashed=False)
+    assert gp.tolist() == [int(v) for v in g["stored_positions"]]
+    val = int("".join(str("ACGT".index(c)) for c in g["shared_minimizer"][0]), 4)
+    assert (val, int(g["shared_minimizer"][1])) in list(zip(gh.tolist(), gp.tolist()))
+
+
+@pytest.mark.parametrize("k,w", [(15, 10), (19, 19), (3, 3), (1, 1), (5, 1), (2, 7), (16, 16),
+                                 (17, 5), (21, 11), (31, 10), (30, 3), (11, 64), (15, 100),
+                                 (7, 255), (13, 1000), (15, 1024)])
+def test_minimizers_random(k, w):
+    torch = torch_cuda()
+    for n in (k + w - 2, k + w - 1, k + w, 200, TILE - 7, 2 * TILE + 333, 5 * TILE + 1):
+        for n_rate in (0.0, 0.03):
+            s = inputs.dna(n, seed=7 * n + k + w, n_rate=n_rate, lowercase_rate=0.02)
+            assert_same_minimizers(torch, s, k, w, tag="random")
+    s = inputs.dna(3 * TILE + 77, seed=k * w, n_rate=0.01)
+    for can in (True, False):
+        for hsh in (True, False):
+            assert_same_minimizers(torch, s, k, w, can, hsh, tag="flags")
+
+
+def test_minimizers_structured():
+    """Repeats and ties (poly-A hashes to 0; tandem repeats tie the hash) and
+    long N runs that empty whole windows and tiles."""
+    torch = torch_cuda()
+    parts = ["A" * 5000, "ACGT" * 1500, "N" * 9000, "AC" * 3000, "T" * 40, "N" * 3,
+             "GATTACA" * 900]
+    s = "".join(parts)
+    for k, w in ((15, 10), (19, 19), (4, 50), (31, 10), (1, 3)):
+        for can in (True, False):
+            for hsh in (True, False):
+                assert_same_minimizers(torch, s, k, w, can, hsh, tag="structured")
+    assert_same_minimizers(torch, "N" * 20000, 15, 10, tag="all-N")
+
+
+def test_minimizers_2bit_and_repeat():
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    for n, n_rate in ((50_000, 0.0), (70_001, 0.01)):
+        s = inputs.dna(n, seed=n, n_rate=n_rate)
+        sd = seq_dev(torch, s)
+        packed, invalid = sws.pack2bit(sd)
+        for use_inv in (True, False):
+            if not use_inv and n_rate > 0:
+                continue
+            h, p = sws.minimizers_2bit(packed, invalid if use_inv else None, n, 15, 10)
+            torch.cuda.synchronize()
+            eh, ep = oracle.minimizers(s, 15, 10)
+            assert np.array_equal(host_u32(p), ep) and np.array_equal(host_u64(h), eh)
+    # the same runner twice: identical, the second call clears its own workspace
+    s = inputs.dna(100_000, seed=5, n_rate=0.01)
+    r = sws.MinimizerRunner(200_000, 15, 10)
+    outs = []
+    for _ in range(2):
+        r.launch(seq=seq_dev(torch, s))
+        h, p = r.result()
+        outs.append((host_u64(h).copy(), host_u32(p).copy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_minimizers_edges():
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    for s in ("", "ACGT", "ACGTACGTACGTACG", "N", "NNNNNNNNNNNNNNNNNNNNNNNNNNNNNNNN"):
+        t = seq_dev(torch, s) if s else torch.empty(0, dtype=torch.uint8, device="cuda")
+        h, p = sws.minimizers(t, 15, 10)
+        torch.cuda.synchronize()
+        eh, ep = oracle.minimizers(s, 15, 10)
+        assert np.array_equal(host_u32(p), ep) and np.array_equal(host_u64(h), eh), s
+
+
+def test_config2_full():
+    """64 Mbases i.i.d. uniform (seed 1), canonical 15-mers, mix64, w = 10:
+    the whole output against the oracle, through both input layouts."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    n = 1 << 26
+    s = inputs.dna(n, seed=1)
+    eh, ep = oracle.minimizers(s, 15, 10)
+    sd = seq_dev(torch, s)
+    h, p = sws.minimizers(sd, 15, 10)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u32(p), ep)
+    assert np.array_equal(host_u64(h), eh)
+    packed, _ = sws.pack2bit(sd, with_invalid=False)
+    h, p = sws.minimizers_2bit(packed, None, n, 15, 10)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u32(p), ep)
+    assert np.array_equal(host_u64(h), eh)
+    W = n - 15 - 10 + 2
+    assert abs(len(ep) / (1 + (W - 1) * 2 / 11) - 1) < 0.005

@@ -1,0 +1,169 @@
+"""Parity of the HIP sliding-sum kernels with the CPU oracle (Eq. 2).
+
+Bit-exact: every operator is integer arithmetic mod 2^32."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev, host_u32, torch_cuda
+from paper_1811_10074_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+S16 = 64 * 16  # elements per wavefront slab (16 per lane)
+
+
+def run(torch, op, w, x, path="auto"):
+    import paper_1811_10074_amd as sws
+    y = sws.sliding_sum(op, w, dev(x, torch), path=path)
+    torch.cuda.synchronize()
+    return host_u32(y)
+
+
+def check(torch, op, w, x, path="auto"):
+    got = run(torch, op, w, x, path)
+    exp = oracle.sliding_sum(op, w, x)
+    assert got.shape == exp.shape, (op, w, path, got.shape, exp.shape)
+    if not np.array_equal(got, exp):
+        bad = np.nonzero(got.reshape(len(got), -1) != exp.reshape(len(exp), -1))[0]
+        raise AssertionError("op=%s w=%d path=%s n=%d: %d mismatches, first at %d"
+                             % (op, w, path, len(x), bad.size, bad[0]))
+
+
+def test_config1_min_and_add():
+    """N = 2^20 uniform u32 (seed 0), w = 16, min and + mod 2^32."""
+    torch = torch_cuda()
+    x = inputs.uniform_u32(1 << 20, seed=0)
+    for op in ("min", "add"):
+        check(torch, op, 16, x)
+    check(torch, "min", 16, x, path="log")
+
+
+WINDOWS = [1, 2, 3, 4, 5, 7, 10, 15, 16, 17, 31, 33, 64, 100, 255, 256, 1000, 1023, 1024, 1025,
+           2047, 2048]
+
+
+@pytest.mark.parametrize("op", ["add", "min", "max", "affine"])
+def test_window_sweep_generic(op):
+    torch = torch_cuda()
+    rng_seed = {"add": 5, "min": 6, "max": 7, "affine": 8}[op]
+    for w in WINDOWS:
+        n = 3 * S16 * 2 + 37 + w  # several slabs plus a ragged tail
+        x = inputs.affine_pairs(n, rng_seed + w, odd=True) if op == "affine" else \
+            inputs.uniform_u32(n, rng_seed + w)
+        check(torch, op, w, x, "generic")
+
+
+@pytest.mark.parametrize("op", ["min", "max"])
+def test_window_sweep_log(op):
+    torch = torch_cuda()
+    for w in WINDOWS + [4095, 4096]:
+        n = 2 * 4096 + 123 + w
+        check(torch, op, w, inputs.uniform_u32(n, 40 + w), "log")
+
+
+@pytest.mark.parametrize("kind", inputs.ADVERSARIAL_KINDS)
+def test_adversarial_inputs(kind):
+    torch = torch_cuda()
+    for w in (4, 16, 17, 64, 1024):
+        x = inputs.adversarial(kind, 5000 + w, w, seed=3)
+        for op in ("add", "min", "max"):
+            check(torch, op, w, x, "generic")
+        for op in ("min", "max"):
+            check(torch, op, w, x, "log")
+
+
+def test_affine_uniform_and_many_waves():
+    """Uniform a (not forced odd) and an input long enough for many waves,
+    each streaming several slabs."""
+    torch = torch_cuda()
+    for w in (4, 16, 64, 256, 1024):
+        x = inputs.affine_pairs(200_003, seed=w)
+        check(torch, "affine", w, x)
+    x = inputs.uniform_u32(3_000_017, seed=9)
+    for w in (16, 1000):
+        check(torch, "add", w, x)
+        check(torch, "max", w, x)
+
+
+def test_edges():
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    for n in (0, 1, 2, 15, 16):
+        x = inputs.uniform_u32(n, 1)
+        for w in (1, 2, 16, 17):
+            for op in ("add", "min"):
+                t = dev(x, torch) if n else torch.empty(0, dtype=torch.int32, device="cuda")
+                y = sws.sliding_sum(op, w, t)
+                torch.cuda.synchronize()
+                assert y.numel() == max(0, n - w + 1)
+                if y.numel():
+                    assert np.array_equal(host_u32(y), oracle.sliding_sum(op, w, x))
+    with pytest.raises(ValueError):
+        sws.sliding_sum("add", 0, dev(inputs.uniform_u32(10, 1), torch))
+    with pytest.raises(ValueError):
+        sws.sliding_sum("add", 4, dev(inputs.uniform_u32(10, 1), torch), path="log")
+
+
+def test_unaligned_pointers():
+    """Views starting 1..3 elements into a buffer take the unaligned path."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    base = inputs.uniform_u32(70_001, 2)
+    t = dev(base, torch)
+    for off in (1, 2, 3):
+        for w in (5, 16, 300):
+            for op in ("add", "min", "max"):
+                y = sws.sliding_sum(op, w, t[off:])
+                torch.cuda.synchronize()
+                assert np.array_equal(host_u32(y), oracle.sliding_sum(op, w, base[off:])), (off, w, op)
+    tp = dev(inputs.affine_pairs(50_001, 3, odd=True), torch)
+    y = sws.sliding_sum("affine", 9, tp[1:])
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u32(y), oracle.sliding_sum("affine", 9, host_u32(tp[1:])))
+
+
+def test_paths_agree_and_repeat():
+    """Generic and log paths agree bit for bit; repeated calls are identical."""
+    torch = torch_cuda()
+    x = inputs.uniform_u32(500_000, 11)
+    for w in (3, 16, 100, 1024):
+        for op in ("min", "max"):
+            a = run(torch, op, w, x, "generic")
+            b = run(torch, op, w, x, "log")
+            c = run(torch, op, w, x, "generic")
+            assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def _sample_check(torch, op, w, x, y, samples, rng):
+    idx = np.concatenate([[0, y.shape[0] - 1], rng.integers(0, y.shape[0], samples)])
+    for i in idx:
+        exp = oracle.sliding_sum(op, w, x[i:i + w])
+        assert np.array_equal(y[i], exp[0]), (op, w, int(i))
+
+
+@pytest.mark.parametrize("op", ["add", "min", "max", "affine"])
+def test_config3_full_size_sampled(op):
+    """N = 2^28 at every window of the sweep, in the bench's launch
+    configuration; sampled outputs against the oracle one by one, and for +
+    the prefix-difference identity over every output."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    n = 1 << 28
+    rng = np.random.default_rng(99)
+    x = inputs.affine_pairs(n, seed=2, odd=True) if op == "affine" else inputs.uniform_u32(n, seed=2)
+    t = dev(x, torch)
+    paths = ["generic", "log"] if op in ("min", "max") else ["generic"]
+    for w in (4, 16, 64, 256, 1024):
+        for path in paths:
+            y = sws.sliding_sum(op, w, t, path=path)
+            torch.cuda.synchronize()
+            yh = host_u32(y)
+            del y
+            _sample_check(torch, op, w, x, yh, 300, rng)
+            if op == "add":
+                pfx = np.zeros(n + 1, dtype=np.uint64)
+                np.cumsum(x, dtype=np.uint64, out=pfx[1:])
+                exp = ((pfx[w:] - pfx[:-w]) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+                assert np.array_equal(yh, exp), w
+                del pfx, exp
