@@ -168,7 +168,10 @@ int sws_minimizers_workspace(uint64_t n, uint32_t k, uint32_t w, uint64_t *bytes
  *   flags     : SWS_KMER_* | SWS_HASH_*.
  *   out_hash  : capacity uint64 (device): value of each stored minimizer.
  *   out_pos   : capacity uint32 (device): its k-mer start position.
- *   d_count   : one uint64 (device): receives the number stored.
+ *   d_count   : one uint64 (device): receives the number stored, or UINT64_MAX
+ *               if the kernel detected an internal error (a tile that waited
+ *               too long for its predecessors' counts; outputs are then
+ *               unusable).
  *   workspace : ws_bytes bytes of device scratch, 8-byte aligned, at least
  *               sws_minimizers_workspace(n, k, w); its contents on entry do
  *               not matter (the call clears what it uses).

@@ -150,6 +150,8 @@ class MinimizerRunner:
     def result(self):
         """Synchronizes, then returns (hash int64[c], pos int32[c]) views."""
         c = int(self.count.item())
+        if c < 0:  # all ones: a tile gave up waiting for its predecessor
+            raise SwsError(_lib.SWS_ERR_DEVICE, "minimizer kernel reported an internal error")
         return self.hash[:c], self.pos[:c]
 
 

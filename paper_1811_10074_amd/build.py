@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
                          if "packed-fp32-ops" not in l)
         if p.returncode != 0:
             failed.append((src, text))
-        elif verbose and text.strip():
+        elif text.strip() and (verbose or "warning" in text):
             print(text)
     if failed:
         msg = "\n".join("%s:\n%s" % f for f in failed)

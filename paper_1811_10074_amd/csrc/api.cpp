@@ -25,7 +25,7 @@ uint32_t bucket_of(uint64_t total_bases, uint64_t nreads) {
 // Smallest tile (most tiles) over the block sizes the library may use: the
 // workspace bound must hold whatever the tuner picks later.
 uint64_t max_tiles(uint64_t nwin, uint32_t w) {
-    const uint32_t tw = sws::minimizer_tile_windows(128, w);
+    const uint32_t tw = sws::minimizer_windows_per_tile(128, w);
     if (tw == 0) return 0;
     return (nwin + tw - 1) / tw;
 }
@@ -55,7 +55,7 @@ int minimizers_common(const sws::GenomeInput& in, uint64_t n, uint32_t k, uint32
     if (nwin > 0 && (out_hash == nullptr || out_pos == nullptr)) return SWS_ERR_INVALID;
     if (capacity < nwin) return SWS_ERR_CAPACITY;
     const uint32_t nt = g_min_block[bucket_of(n, 1)];
-    const uint32_t tw = sws::minimizer_tile_windows(nt, w);
+    const uint32_t tw = sws::minimizer_windows_per_tile(nt, w);
     const uint64_t ntiles = nwin ? (nwin + tw - 1) / tw : 0;
     const uint64_t need = sws::minimizer_workspace_bytes(max_tiles(nwin, w));
     if (workspace == nullptr || ws_bytes < need || ((uintptr_t)workspace & 7u)) return SWS_ERR_WORKSPACE;

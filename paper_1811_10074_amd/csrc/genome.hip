@@ -18,10 +18,10 @@
 //      "leftmost minimum" operator, which is associative;
 //   4. a window's minimizer is stored iff it exists and its position differs
 //      from the previous window's (same position <=> same pair);
-//   5. ordered compaction: a block scan of the per-lane store counts, then a
-//      decoupled look-back over the tiles (tile ids from an atomic counter, so
-//      a tile only waits for tiles that are already running), then coalesced
-//      stores from an LDS staging area.
+//   5. ordered compaction: a scan of the per-lane store counts, then a
+//      decoupled look-back over the tiles (tile order = workgroup order, so a
+//      tile only waits for tiles of workgroups dispatched before its own),
+//      then coalesced stores from an LDS staging area.
 //
 // Tile geometry: 16 positions per lane, P = 16 * NT key positions per tile
 // starting at K0 = p0 - 16, where p0 (a multiple of 16) is the first window
@@ -193,6 +193,76 @@ __device__ __forceinline__ void stage_bases(const GenomeInput& in, int64_t K0, i
     }
 }
 
+// The 16-base words a wavefront's tile needs, split in two phases so that the
+// global loads of the next tile can be in flight while the current one is
+// computed: `fetch` issues the loads into registers, `commit` converts and
+// stores them into LDS.  Lane l holds word l, and lanes 0 and 1 also words
+// 64 and 65.
+struct RawWords {
+    uint4 a, b;  // ASCII: 16 bytes each; 2-bit: .x code word, .y invalid bits
+};
+
+template <int IN>
+__device__ __forceinline__ void fetch_words(const GenomeInput& in, int64_t K0, int lane,
+                                            RawWords& r) {
+    const int64_t b0 = K0 + 16 * (int64_t)lane;
+    const int64_t b1 = K0 + 16 * (int64_t)(kWave + lane);
+    if (IN == kInAscii) {
+        const bool fast0 = in.aligned && b0 >= 0 && (uint64_t)b0 + 16 <= in.n;
+        const bool fast1 = in.aligned && b1 >= 0 && (uint64_t)b1 + 16 <= in.n;
+        r.a = fast0 ? *reinterpret_cast<const uint4*>(in.seq + b0) : make_uint4(0, 0, 0, 0);
+        r.b = (lane < 2 && fast1) ? *reinterpret_cast<const uint4*>(in.seq + b1)
+                                  : make_uint4(0, 0, 0, 0);
+    } else {
+        uint32_t c, v;
+        packed16(in.packed, in.invalid, b0, in.n, c, v);
+        r.a = make_uint4(c, v, 0, 0);
+        if (lane < 2) packed16(in.packed, in.invalid, b1, in.n, c, v);
+        r.b = make_uint4(c, v, 0, 0);
+    }
+}
+
+__device__ __forceinline__ void ascii_word(const GenomeInput& in, int64_t base, const uint4& q,
+                                           uint32_t& code, uint32_t& inv) {
+    if (in.aligned && base >= 0 && (uint64_t)base + 16 <= in.n) {
+        const uint32_t word[4] = {q.x, q.y, q.z, q.w};
+        code = 0;
+        inv = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t b = (word[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+            const bool ok = base_valid(b);
+            code |= (ok ? base_code(b) : 0u) << (30 - 2 * i);
+            inv |= (ok ? 0u : 1u) << i;
+        }
+    } else {
+        ascii16(in.seq, base, in.n, false, code, inv);  // edges and unaligned input
+    }
+}
+
+template <int IN>
+__device__ __forceinline__ void commit_words(const GenomeInput& in, int64_t K0, int lane,
+                                             const RawWords& r, uint32_t* code, uint32_t* inv) {
+    if (IN == kInAscii) {
+        uint32_t c, v;
+        ascii_word(in, K0 + 16 * (int64_t)lane, r.a, c, v);
+        code[lane] = c;
+        inv[lane] = v;
+        if (lane < 2) {
+            ascii_word(in, K0 + 16 * (int64_t)(kWave + lane), r.b, c, v);
+            code[kWave + lane] = c;
+            inv[kWave + lane] = v;
+        }
+    } else {
+        code[lane] = r.a.x;
+        inv[lane] = r.a.y;
+        if (lane < 2) {
+            code[kWave + lane] = r.b.x;
+            inv[kWave + lane] = r.b.y;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // pack2bit: one lane per 16 bases.
 // ---------------------------------------------------------------------------
@@ -263,38 +333,76 @@ struct OpKeyMin {
 
 __device__ __forceinline__ uint32_t pad16(uint32_t i) { return i + (i >> 4); }
 
-// Exclusive prefix of the tile's store count over the tiles before it.
-__device__ uint64_t tile_lookback(uint64_t* status, uint64_t tile, uint64_t total,
-                                  uint32_t* err) {
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t lo = shfl((uint32_t)v, lane, d);
+        const uint32_t hi = shfl((uint32_t)(v >> 32), lane, d);
+        v += ((uint64_t)hi << 32) | lo;  // lanes past 63 wrap; lane 0 ends with the total
+    }
+    return v;
+}
+
+// Exclusive prefix of the tile's store count over the tiles before it
+// (decoupled look-back, one wavefront).  Each tile first publishes its own
+// count (AGGREGATE), then reads the status words of the 64 tiles before it in
+// one round: if every tile back to the nearest one with an INCLUSIVE prefix
+// has published, their counts plus that prefix give the answer; otherwise it
+// waits and re-reads.  Without an INCLUSIVE word among the 64 it moves 64
+// further back.  Called by all 64 lanes of one wave; returns the prefix in
+// every lane.
+__device__ uint64_t tile_lookback(uint64_t* status, uint64_t tile, uint64_t total, uint32_t* err,
+                                  int lane) {
     const uint64_t kAgg = 1ull << 62, kInc = 2ull << 62, kVal = (1ull << 62) - 1ull;
     if (tile == 0) {
-        __hip_atomic_store(&status[0], kInc | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0)
+            __hip_atomic_store(&status[0], kInc | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return 0;
     }
-    __hip_atomic_store(&status[tile], kAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0)
+        __hip_atomic_store(&status[tile], kAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint64_t excl = 0;
-    uint64_t j = tile - 1;
+    int64_t base = (int64_t)tile - 1;
     uint32_t spins = 0;
     for (;;) {
-        const uint64_t s = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t j = base - lane;
+        // before tile 0 there is nothing: read as an INCLUSIVE prefix of 0
+        const uint64_t s = j >= 0 ? __hip_atomic_load(&status[j], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)
+                                  : kInc;
         const uint64_t f = s >> 62;
-        if (f == 0) {
+        const uint64_t inc = __ballot(f == 2);
+        const uint64_t notready = __ballot(f == 0);
+        const int first = inc ? __builtin_ctzll(inc) : kWave;  // nearest INCLUSIVE lane
+        const uint64_t need = first >= kWave - 1 ? ~0ull : ((2ull << first) - 1ull);
+        if (notready & need) {
             // Bounded wait: a predecessor that never publishes (which a correct
             // launch cannot produce) flags an error instead of hanging.
-            if (++spins > (1u << 22)) {
-                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (++spins > (1u << 20)) {
+                if (lane == 0)
+                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        excl += s & kVal;
-        if (f == 2) break;
-        --j;
+        const uint64_t mine = lane <= first ? (s & kVal) : 0ull;
+        excl += lane_value_u64(wave_sum_u64(mine, lane), 0);
+        if (first < kWave) break;
+        base -= kWave;
     }
-    __hip_atomic_store(&status[tile], kInc | (excl + total), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0)
+        __hip_atomic_store(&status[tile], kInc | (excl + total), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     return excl;
+}
+
+// The count the last tile reports: the total, or all ones if some tile gave
+// up waiting for a predecessor (an internal error the caller must see).
+__device__ __forceinline__ uint64_t final_count(uint32_t* err, uint64_t total) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? ~0ull : total;
 }
 
 template <int NT, int IN, bool KM64, bool FULL>
@@ -310,16 +418,15 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
     __shared__ Key s_carryF[NWV], s_carryB[NWV];
     __shared__ uint32_t s_lastTag[NWV];
     __shared__ uint32_t s_wsum[NWV];
-    __shared__ uint64_t s_tile, s_excl;
+    __shared__ uint64_t s_excl;
 
     const int tid = (int)threadIdx.x;
     const int lane = lane_id();
     const int wv = tid >> 6;
     const uint32_t w = a.w;
 
-    if (tid == 0) s_tile = atomicAdd((unsigned long long*)a.counter, 1ull);
-    __syncthreads();
-    const uint64_t tile = s_tile;
+    // tile order = workgroup order (see minimizer_wave_kernel)
+    const uint64_t tile = blockIdx.x;
     const int64_t p0 = (int64_t)(tile * a.tw);
     const int64_t K0 = p0 - 16;
 
@@ -349,8 +456,10 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
     //    aligned to multiples of w inside the tile
     const uint32_t span = (w + kR - 1) / kR;
     const uint32_t m0 = ((uint32_t)tid * kR) % w;
-    slab_prefix<Op, kR>(pf, m0, w, span, lane, Op::identity());
-    slab_suffix<Op, kR>(sf, m0, w, span, lane);
+    uint64_t heads, ends;
+    lane_masks<kR>(m0, w, head_pattern(w, kR), heads, ends);
+    slab_prefix<Op, kR>(pf, heads, span, lane, Op::identity());
+    slab_suffix<Op, kR>(sf, ends, span, lane);
     if (lane == kWave - 1) s_carryF[wv] = pf[kR - 1];
     if (lane == 0) s_carryB[wv] = sf[0];
 #pragma unroll
@@ -386,13 +495,11 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
                 r.hi = (uint32_t)(h >> 32);
                 r.tag = s_tag[pad16(q)];
                 // prefix minima of a segment that started in the previous wave
+                // a segment that started in the previous wave takes that wave's
+                // carried prefix; q mod w = (j - 1) mod w
                 const uint32_t qw = q / WS;
-                if (qw > 0) {
-                    const uint32_t ws0 = qw * WS;
-                    const uint32_t rem = ws0 % w;
-                    const uint32_t first_head = rem == 0u ? ws0 : ws0 + (w - rem);
-                    if (q < first_head) r = Op::combine(s_carryF[qw - 1], r);
-                }
+                const uint32_t qhead = q - (m == 0u ? w - 1u : m - 1u);
+                if (qhead < qw * WS) r = Op::combine(s_carryF[qw - 1], r);
                 if (m != 0u) r = Op::combine(sf[e], r);
             } else {
                 r = Op::identity();
@@ -449,7 +556,10 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
             ++slot;
         }
     }
-    if (tid == 0) s_excl = tile_lookback(a.status, tile, total, a.err);
+    if (wv == 0) {
+        const uint64_t e = tile_lookback(a.status, tile, total, a.err, lane);
+        if (lane == 0) s_excl = e;
+    }
     __syncthreads();
     const uint64_t excl = s_excl;
     for (uint32_t i = (uint32_t)tid; i < total; i += NT) {
@@ -459,7 +569,168 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
             a.out_pos[g] = (uint32_t)(K0 + (int64_t)s_tag[i]);
         }
     }
-    if (tid == 0 && tile == a.ntiles - 1) *a.d_count = excl + total;
+    if (tid == 0 && tile == a.ntiles - 1) *a.d_count = final_count(a.err, excl + total);
+}
+
+// ---------------------------------------------------------------------------
+// Minimizers, one wavefront per tile (w <= 32).
+//
+// Each wavefront owns a tile of 1024 key positions (16 per lane) and does every
+// step alone: no workgroup barrier after the tile id is known.  The window
+// minimum uses the doubling of Sec. 3.1 for an idempotent operator: with
+// m^(1) = key, m^(2s)_e = min(m^(s)_e, m^(s)_{e+s}), and 2^L the largest power
+// of two not above w, the minimum over [e, e+w) is min(m^(2^L)_e,
+// m^(2^L)_{e+w-2^L}) -- the two halves overlap, which min allows.  The levels
+// run in registers (a lane takes the s values it needs past its run from the
+// next lane); the last, runtime-length shift goes through LDS.  Every min keeps
+// the left operand on ties, so the leftmost position wins.
+// ---------------------------------------------------------------------------
+constexpr int kWaveKeys = kWave * kR;  // 1024 keys per wave tile
+constexpr int kWaveWords = kWaveKeys / 16 + 2;
+constexpr int kWaveSlots = kWaveKeys + 2 * kWave;  // keys + room for dumped lanes
+
+template <bool FULL>
+__device__ __forceinline__ Key key_min(const Key& l, const Key& r) {
+    return OpKeyMin<FULL>::combine(l, r);
+}
+
+template <int NT, int IN, bool KM64, bool FULL>
+__global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, MinimizerArgs a) {
+    constexpr int NWV = NT / kWave;
+    __shared__ uint32_t s_code[NWV][kWaveWords], s_inv[NWV][kWaveWords];
+    __shared__ uint64_t s_h[NWV][kWaveSlots + kWaveSlots / 16];
+    __shared__ uint16_t s_tag[NWV][kWaveSlots + kWaveSlots / 16];
+
+    const int lane = lane_id();
+    const int wv = (int)(threadIdx.x >> 6);
+    const uint32_t w = a.w;
+    uint32_t* code = s_code[wv];
+    uint32_t* inv = s_inv[wv];
+    uint64_t* sh = s_h[wv];
+    uint16_t* stag = s_tag[wv];
+
+    // Tile order = workgroup order.  A tile waits (look-back) only for tiles
+    // of lower index, which belong to workgroups dispatched before it; the
+    // lowest unfinished tile never waits, so every tile finishes.
+    const uint64_t cur = (uint64_t)blockIdx.x * NWV + (uint64_t)wv;
+    if (cur >= a.ntiles) return;
+    RawWords raw;
+    fetch_words<IN>(in, (int64_t)(cur * a.tw) - 16, lane, raw);
+    {
+        const int64_t p0 = (int64_t)(cur * a.tw);
+        const int64_t K0 = p0 - 16;
+
+        // 1. bases (loaded during the previous tile)
+        commit_words<IN>(in, K0, lane, raw, code, inv);
+        wave_lds_sync();
+
+        // 2. keys
+        Key m[kR];
+        {
+            uint64_t val[kR];
+            uint32_t bad;
+            lane_kmers<KM64>(code, inv, lane, a.k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u,
+                             val, bad);
+#pragma unroll
+            for (int e = 0; e < kR; ++e) {
+                const bool iv = (bad >> e) & 1u;
+                m[e].lo = iv ? 0xFFFFFFFFu : (uint32_t)val[e];
+                m[e].hi = iv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
+                m[e].tag = ((uint32_t)lane * kR + e) | (iv ? kInvalidTag : 0u);
+            }
+        }
+
+        // 3. window minimum by doubling: levels 1, 2, 4, 8, 16 while 2s <= w
+        uint32_t L = 1;
+#pragma unroll
+        for (int s = 1; s <= 16; s *= 2) {
+            if ((uint32_t)(2 * s) <= w) {
+                Key nb[16];
+#pragma unroll
+                for (int t = 0; t < s; ++t) nb[t] = shfl(m[t], lane, 1);
+#pragma unroll
+                for (int e = 0; e < kR; ++e) {
+                    const Key r = (e + s < kR) ? m[e + s] : nb[e + s - kR];
+                    m[e] = key_min<FULL>(m[e], r);
+                }
+                L = 2u * (uint32_t)s;
+            }
+        }
+        const uint32_t shift = w - L;  // 0 <= shift < L <= 16
+        if (shift != 0u) {
+#pragma unroll
+            for (int e = 0; e < kR; ++e) {
+                const uint32_t j = (uint32_t)lane * kR + e;
+                sh[pad16(j)] = ((uint64_t)m[e].hi << 32) | m[e].lo;
+                stag[pad16(j)] = (uint16_t)m[e].tag;
+            }
+            if (lane < 1) {  // keys past the tile read as invalid
+#pragma unroll
+                for (int e = 0; e < kR; ++e) {
+                    sh[pad16(kWaveKeys + e)] = ~0ull;
+                    stag[pad16(kWaveKeys + e)] = 0xFFFFu;
+                }
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int e = 0; e < kR; ++e) {
+                const uint32_t q = (uint32_t)lane * kR + e + shift;
+                Key r;
+                const uint64_t h = sh[pad16(q)];
+                r.lo = (uint32_t)h;
+                r.hi = (uint32_t)(h >> 32);
+                r.tag = stag[pad16(q)];
+                m[e] = key_min<FULL>(m[e], r);
+            }
+            wave_lds_sync();
+        }
+
+        // 4. dedup: window j is stored iff owned, valid and at a new position
+        uint32_t emit = 0;
+        {
+            uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
+#pragma unroll
+            for (int e = 0; e < kR; ++e) {
+                const uint32_t j = (uint32_t)lane * kR + e;
+                const int64_t p = K0 + (int64_t)j;
+                const bool owned = j >= 16u && j < 16u + a.tw && p < (int64_t)a.nwin;
+                const bool valid = (m[e].tag & kInvalidTag) == 0u;
+                const bool fresh = p == 0 || m[e].tag != prev;
+                emit |= (owned && valid && fresh ? 1u : 0u) << e;
+                prev = m[e].tag;
+            }
+        }
+
+        // 5. ordered compaction: lane prefix, look-back, staged coalesced stores
+        const uint32_t cnt = (uint32_t)__builtin_popcount(emit);
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = shfl(incl, lane, -d);
+            if (lane >= d) incl += o;
+        }
+        const uint32_t total = lane_value(incl, kWave - 1);
+        uint32_t slot = incl - cnt;
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const bool on = (emit >> e) & 1u;
+            // lanes with nothing to store write into their own dump slot
+            const uint32_t at = on ? slot : (uint32_t)(kWaveKeys + kWave + lane);
+            sh[at] = ((uint64_t)m[e].hi << 32) | m[e].lo;
+            stag[at] = (uint16_t)(m[e].tag & 0x7FFFu);
+            slot += on ? 1u : 0u;
+        }
+        const uint64_t excl = tile_lookback(a.status, cur, total, a.err, lane);
+        wave_lds_sync();
+        for (uint32_t i = (uint32_t)lane; i < total; i += kWave) {
+            const uint64_t g = excl + i;
+            if (g < a.capacity) {
+                a.out_hash[g] = sh[i];
+                a.out_pos[g] = (uint32_t)(K0 + (int64_t)stag[i]);
+            }
+        }
+        if (lane == 0 && cur == a.ntiles - 1) *a.d_count = final_count(a.err, excl + total);
+    }
 }
 
 __global__ void zero_words_kernel(uint64_t* __restrict__ p, uint64_t count) {
@@ -514,7 +785,32 @@ uint32_t minimizer_tile_windows(uint32_t nt, uint32_t w) {
     return (P - 16u - (w - 1u)) & ~15u;
 }
 
+uint32_t minimizer_wave_max_window() { return 32; }
+
+// Windows stored per tile: one wavefront's 1024 keys when w <= 32, else the
+// workgroup's 16 * nt keys.
+uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t w) {
+    return w <= minimizer_wave_max_window() ? minimizer_tile_windows(kWave, w)
+                                            : minimizer_tile_windows(nt, w);
+}
+
 uint64_t minimizer_workspace_bytes(uint64_t ntiles) { return kWsStatusOffset + 8ull * ntiles; }
+
+template <int NT, int IN, bool KM64, bool FULL>
+static void launch_wave_variant(const GenomeInput& in, const MinimizerArgs& a, hipStream_t s) {
+    constexpr int NWV = NT / kWave;
+    const unsigned grid = (unsigned)((a.ntiles + NWV - 1) / NWV);
+    hipLaunchKernelGGL((minimizer_wave_kernel<NT, IN, KM64, FULL>), dim3(grid), dim3(NT), 0, s,
+                       in, a);
+}
+
+template <int NT, int IN>
+static void launch_min_wave(const GenomeInput& in, const MinimizerArgs& a, bool km64, bool full,
+                            hipStream_t s) {
+    if (!km64) launch_wave_variant<NT, IN, false, false>(in, a, s);
+    else if (!full) launch_wave_variant<NT, IN, true, false>(in, a, s);
+    else launch_wave_variant<NT, IN, true, true>(in, a, s);
+}
 
 template <int NT, int IN>
 static void launch_min_nt(const GenomeInput& in, const MinimizerArgs& a, bool km64, bool full,
@@ -538,6 +834,11 @@ int launch_minimizers(const GenomeInput& in, MinimizerArgs a, uint32_t nt, void*
         return -1;
     const bool km64 = a.k > 16;
     const bool full = a.k >= 30 && (a.flags & 2u) == 0u;
+    if (a.w <= minimizer_wave_max_window()) {
+        if (in.kind == kInAscii) launch_min_wave<256, kInAscii>(in, a, km64, full, s);
+        else launch_min_wave<256, kIn2bit>(in, a, km64, full, s);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
     if (in.kind == kInAscii) {
         if (nt == 128) launch_min_nt<128, kInAscii>(in, a, km64, full, s);
         else if (nt == 512) launch_min_nt<512, kInAscii>(in, a, km64, full, s);

@@ -41,17 +41,105 @@ namespace sws {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t ring_index(uint32_t r) { return r + (r >> 4); }
 
+// Coalesced movement of one slab between HBM and a lane's run of R elements:
+// lane l loads/stores the 16-byte chunks l, l + 64, l + 128, ... of the slab
+// (every instruction covers 1 KB of contiguous memory) and the chunks change
+// hands through a per-wave LDS staging area padded by 16 bytes per run.
+template <class T, int R>
+struct SlabIO {
+    static constexpr int kChunks = (int)(R * sizeof(T) / 16);  // chunks per lane run
+    static constexpr int kStageWords = kWave * (kChunks + 1) * 4;
+
+    static __device__ __forceinline__ uint32_t stage_off(int chunk) {  // in u32 words
+        return (uint32_t)((chunk / kChunks) * (kChunks + 1) + chunk % kChunks) * 4u;
+    }
+
+    // raw[i] = chunk (i * 64 + lane) of the slab starting at element p0;
+    // elements at or past n read as the identity.
+    static __device__ __forceinline__ void load(const T* __restrict__ x, uint64_t n, uint64_t p0,
+                                                int lane, bool vec, T ident, u32x4 (&raw)[kChunks]) {
+        const uint64_t per = 16 / sizeof(T);
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const uint64_t e0 = p0 + (uint64_t)(i * kWave + lane) * per;
+            if (vec && e0 + per <= n) {
+                raw[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(x + e0));
+            } else {
+                const uint32_t* xw = reinterpret_cast<const uint32_t*>(x);
+                const uint32_t* iw = reinterpret_cast<const uint32_t*>(&ident);
+                constexpr int wpe = (int)(sizeof(T) / 4);  // words per element
+                u32x4 c;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t e = e0 + (uint64_t)(q / wpe);
+                    c[q] = e < n ? xw[e * wpe + (q % wpe)] : iw[q % wpe];
+                }
+                raw[i] = c;
+            }
+        }
+    }
+
+    // raw chunks -> this lane's run, through the staging area
+    static __device__ __forceinline__ void to_run(uint32_t* stage, int lane,
+                                                  const u32x4 (&raw)[kChunks], T (&v)[R]) {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            *reinterpret_cast<u32x4*>(stage + stage_off(i * kWave + lane)) = raw[i];
+        wave_lds_sync();
+        u32x4 q[kChunks];
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            q[i] = *reinterpret_cast<const u32x4*>(stage + stage_off(lane * kChunks + i));
+        const T* t = reinterpret_cast<const T*>(q);
+#pragma unroll
+        for (int e = 0; e < R; ++e) v[e] = t[e];
+        wave_lds_sync();
+    }
+
+    // this lane's run -> coalesced stores of the slab at element p0 (below limit)
+    static __device__ __forceinline__ void store(T* __restrict__ y, uint64_t limit, uint64_t p0,
+                                                 int lane, bool vec, uint32_t* stage,
+                                                 const T (&v)[R]) {
+        const u32x4* q = reinterpret_cast<const u32x4*>(v);
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            *reinterpret_cast<u32x4*>(stage + stage_off(lane * kChunks + i)) = q[i];
+        wave_lds_sync();
+        const uint64_t per = 16 / sizeof(T);
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const u32x4 c = *reinterpret_cast<const u32x4*>(stage + stage_off(i * kWave + lane));
+            const uint64_t e0 = p0 + (uint64_t)(i * kWave + lane) * per;
+            if (vec && e0 + per <= limit) {
+                __builtin_nontemporal_store(c, reinterpret_cast<u32x4*>(y + e0));
+            } else {
+                uint32_t* yw = reinterpret_cast<uint32_t*>(y);
+                constexpr int wpe = (int)(sizeof(T) / 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t e = e0 + (uint64_t)(q / wpe);
+                    if (e < limit) yw[e * wpe + (q % wpe)] = c[q];
+                }
+            }
+        }
+        wave_lds_sync();
+    }
+};
+
 template <class Op, int R, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
     const typename Op::T* __restrict__ x, uint64_t n, uint32_t w, typename Op::T* __restrict__ y,
     uint64_t count, uint64_t total_slabs, uint64_t slabs_per_wave, int vec) {
     using T = typename Op::T;
+    using IO = SlabIO<T, R>;
     constexpr uint32_t S = kWave * R;
     constexpr uint32_t RING = 2 * S;
     __shared__ T ring_all[WAVES][RING + RING / 16];
+    __shared__ uint32_t stage_all[WAVES][IO::kStageWords];
     const int lane = lane_id();
     const int wv = (int)(threadIdx.x >> 6);
     T* ring = ring_all[wv];
+    uint32_t* stage = stage_all[wv];
     const uint64_t gw = (uint64_t)blockIdx.x * WAVES + (uint64_t)wv;
     const uint64_t s0 = gw * slabs_per_wave;
     if (s0 >= total_slabs) return;
@@ -60,46 +148,56 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
     const uint32_t span = (w + R - 1) / R;
     const uint32_t lane_mod = (uint32_t)((uint32_t)(lane * R) % w);
     const uint32_t slab_mod_step = S % w;
+    const uint64_t pat = head_pattern(w, R);
     const T ident = Op::identity();
+    const bool v16 = vec != 0;
 
-    // state of slab A = s0
+    // slab A = s0: prefix sums into ring half 0, suffix sums in registers
     uint32_t mA = (uint32_t)((s0 * (uint64_t)S) % w);
+    uint64_t headsA, endsA;
     T sfA[R];
     T carryA;
+    u32x4 raw[IO::kChunks];
+    IO::load(x, n, s0 * S, lane, v16, ident, raw);
     {
         T v[R];
-        load_run<T, R>(x, n, s0 * S + (uint64_t)lane * R, vec != 0, ident, v);
+        IO::to_run(stage, lane, raw, v);
         uint32_t m0 = mA + lane_mod;
         m0 = m0 >= w ? m0 - w : m0;
+        lane_masks<R>(m0, w, pat, headsA, endsA);
 #pragma unroll
         for (int e = 0; e < R; ++e) sfA[e] = v[e];
-        slab_prefix<Op, R>(v, m0, w, span, lane, ident);
+        slab_prefix<Op, R>(v, headsA, span, lane, ident);
 #pragma unroll
         for (int e = 0; e < R; ++e) ring[ring_index((uint32_t)lane * R + e)] = v[e];
         carryA = lane_value(v[R - 1], kWave - 1);
-        slab_suffix<Op, R>(sfA, m0, w, span, lane);
+        slab_suffix<Op, R>(sfA, endsA, span, lane);
     }
+    IO::load(x, n, (s0 + 1) * S, lane, v16, ident, raw);  // slab B
     uint32_t half = 0;  // ring half holding slab A's prefix sums
 
     for (uint64_t s = s0; s < s1; ++s) {
         const uint64_t baseA = s * S;
         uint32_t mB = mA + slab_mod_step;
         mB = mB >= w ? mB - w : mB;
-        // slab B = s + 1: prefix sums into the other ring half, suffix sums kept
         T sfB[R];
+        uint64_t headsB, endsB;
         {
             T v[R];
-            load_run<T, R>(x, n, baseA + S + (uint64_t)lane * R, vec != 0, ident, v);
+            IO::to_run(stage, lane, raw, v);
+            // prefetch slab s + 2 while B and A are computed
+            if (s + 1 < s1) IO::load(x, n, baseA + 2 * (uint64_t)S, lane, v16, ident, raw);
             uint32_t m0 = mB + lane_mod;
             m0 = m0 >= w ? m0 - w : m0;
+            lane_masks<R>(m0, w, pat, headsB, endsB);
 #pragma unroll
             for (int e = 0; e < R; ++e) sfB[e] = v[e];
-            slab_prefix<Op, R>(v, m0, w, span, lane, carryA);
+            slab_prefix<Op, R>(v, headsB, span, lane, carryA);
             const uint32_t off = (half ^ 1u) * S;
 #pragma unroll
             for (int e = 0; e < R; ++e) ring[ring_index(off + (uint32_t)lane * R + e)] = v[e];
             carryA = lane_value(v[R - 1], kWave - 1);
-            slab_suffix<Op, R>(sfB, m0, w, span, lane);
+            slab_suffix<Op, R>(sfB, endsB, span, lane);
         }
         // the last segment of A continues into B: append B's leading suffix
         {
@@ -113,24 +211,21 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
             }
         }
         wave_lds_sync();
-        // outputs of slab A
+        // outputs of slab A: y_i = Pf_{i+w-1} at a head, Sf_i (+) Pf_{i+w-1} elsewhere
         {
             T out[R];
-            uint32_t m = mA + lane_mod;
-            m = m >= w ? m - w : m;
             const uint32_t aoff = half * S;
 #pragma unroll
             for (int e = 0; e < R; ++e) {
                 const uint32_t r = (aoff + (uint32_t)lane * R + e + w - 1u) & (RING - 1u);
                 const T pf = ring[ring_index(r)];
-                out[e] = (m == 0u) ? pf : Op::combine(sfA[e], pf);
-                m = (m + 1u == w) ? 0u : m + 1u;
+                out[e] = ((headsA >> e) & 1ull) ? pf : Op::combine(sfA[e], pf);
             }
-            store_run<T, R>(y, count, baseA + (uint64_t)lane * R, vec != 0, out);
+            IO::store(y, count, baseA, lane, v16, stage, out);
         }
-        wave_lds_sync();
 #pragma unroll
         for (int e = 0; e < R; ++e) sfA[e] = sfB[e];
+        headsA = headsB;
         mA = mB;
         half ^= 1u;
     }
@@ -206,7 +301,8 @@ static int launch_log(const void* x, uint64_t n, uint32_t w, void* y, uint64_t c
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Windows up to 64*16 elements use 16 elements per lane; up to 64*32, 32.
+// Elements per lane and waves per workgroup: a window must fit in one slab of
+// 64 * R elements; LDS per wave is the ring of two slabs plus the staging area.
 uint32_t generic_max_window() { return kWave * 32; }
 
 // A tile of 4096 outputs plus a halo of w-1 in two LDS buffers stays within 64 KB.
@@ -216,14 +312,16 @@ int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* 
                            hipStream_t s) {
     const bool big = w > (uint32_t)(kWave * 16);
     switch (op) {
-    case kOpAdd: return big ? launch_generic<OpAdd, 32, 2>(x, n, w, y, count, s)
-                            : launch_generic<OpAdd, 16, 4>(x, n, w, y, count, s);
-    case kOpMin: return big ? launch_generic<OpMin, 32, 2>(x, n, w, y, count, s)
-                            : launch_generic<OpMin, 16, 4>(x, n, w, y, count, s);
-    case kOpMax: return big ? launch_generic<OpMax, 32, 2>(x, n, w, y, count, s)
-                            : launch_generic<OpMax, 16, 4>(x, n, w, y, count, s);
-    case kOpAffine: return big ? launch_generic<OpAffine, 32, 1>(x, n, w, y, count, s)
-                               : launch_generic<OpAffine, 16, 4>(x, n, w, y, count, s);
+    case kOpAdd: return big ? launch_generic<OpAdd, 32, 1>(x, n, w, y, count, s)
+                            : launch_generic<OpAdd, 16, 2>(x, n, w, y, count, s);
+    case kOpMin: return big ? launch_generic<OpMin, 32, 1>(x, n, w, y, count, s)
+                            : launch_generic<OpMin, 16, 2>(x, n, w, y, count, s);
+    case kOpMax: return big ? launch_generic<OpMax, 32, 1>(x, n, w, y, count, s)
+                            : launch_generic<OpMax, 16, 2>(x, n, w, y, count, s);
+    case kOpAffine:
+        if (big) return launch_generic<OpAffine, 32, 1>(x, n, w, y, count, s);
+        if (w > (uint32_t)(kWave * 8)) return launch_generic<OpAffine, 16, 1>(x, n, w, y, count, s);
+        return launch_generic<OpAffine, 8, 2>(x, n, w, y, count, s);
     default: return -2;
     }
 }

@@ -74,6 +74,10 @@ __device__ __forceinline__ uint2 lane_value(uint2 v, int src) {
     return make_uint2(lane_value(v.x, src), lane_value(v.y, src));
 }
 
+__device__ __forceinline__ uint64_t lane_value_u64(uint64_t v, int src) {
+    return ((uint64_t)lane_value((uint32_t)(v >> 32), src) << 32) | lane_value((uint32_t)v, src);
+}
+
 __device__ __forceinline__ Key lane_value(Key v, int src) {
     Key r;
     r.lo = lane_value(v.lo, src);

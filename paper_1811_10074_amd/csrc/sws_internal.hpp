@@ -48,6 +48,7 @@ int launch_pack2bit(const uint8_t* seq, uint64_t n, uint32_t* packed, uint32_t* 
                     hipStream_t s);
 int launch_kmers(const GenomeInput& in, uint32_t k, uint32_t flags, uint64_t* out, hipStream_t s);
 uint32_t minimizer_tile_windows(uint32_t nt, uint32_t w);
+uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t w);
 uint64_t minimizer_workspace_bytes(uint64_t ntiles);
 int launch_minimizers(const GenomeInput& in, MinimizerArgs a, uint32_t nt, void* workspace,
                       hipStream_t s);

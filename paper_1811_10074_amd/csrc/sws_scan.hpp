@@ -48,26 +48,38 @@ __device__ __forceinline__ void store_run(T* __restrict__ y, uint64_t limit, uin
     }
 }
 
-// In-segment prefix sums of one slab.  m0 = (position of the lane's first
-// element) mod w.  carry = prefix at the last element of the previous slab.
+// Bits at every multiple of w in [0, R]: shifted by a lane's first head offset
+// it marks the lane's segment heads.
+__device__ __forceinline__ uint64_t head_pattern(uint32_t w, int R) {
+    uint64_t p = 0;
+    for (uint32_t j = 0; j <= (uint32_t)R; j += w) p |= 1ull << j;
+    return p;
+}
+
+// Segment heads (bit e: element e starts a segment) and ends (bit e: element e
+// is the last of its segment) of a lane whose first element has index
+// m0 mod w.
+template <int R>
+__device__ __forceinline__ void lane_masks(uint32_t m0, uint32_t w, uint64_t pat, uint64_t& heads,
+                                           uint64_t& ends) {
+    const uint32_t f = m0 == 0u ? 0u : w - m0;  // offset of the first head
+    const uint64_t span = (R + 1 >= 64) ? ~0ull : ((1ull << (R + 1)) - 1ull);
+    const uint64_t h = f <= (uint32_t)R ? ((pat << f) & span) : 0ull;
+    heads = h & ((R >= 64) ? ~0ull : ((1ull << R) - 1ull));
+    ends = h >> 1;
+}
+
+// In-segment prefix sums of one slab.  heads: the lane's segment heads.
+// carry = prefix at the last element of the previous slab (identity if none).
 template <class Op, int R>
-__device__ __forceinline__ void slab_prefix(typename Op::T (&v)[R], uint32_t m0, uint32_t w,
-                                            uint32_t span, int lane, typename Op::T carry) {
+__device__ __forceinline__ void slab_prefix(typename Op::T (&v)[R], uint64_t heads, uint32_t span,
+                                            int lane, typename Op::T carry) {
     using T = typename Op::T;
-    uint32_t headmask = 0;
-    {
-        uint32_t m = m0;
-#pragma unroll
-        for (int e = 0; e < R; ++e) {
-            headmask |= (m == 0u ? 1u : 0u) << e;
-            m = (m + 1u == w) ? 0u : m + 1u;
-        }
-    }
 #pragma unroll
     for (int e = 1; e < R; ++e)
-        if (!((headmask >> e) & 1u)) v[e] = Op::combine(v[e - 1], v[e]);
+        if (!((heads >> e) & 1ull)) v[e] = Op::combine(v[e - 1], v[e]);
     // segmented inclusive scan of (has head, value) across lanes
-    uint32_t F = headmask != 0u;
+    uint32_t F = heads != 0ull;
     T V = v[R - 1];
     for (uint32_t d = 1; d < span; d <<= 1) {
         const uint32_t Fo = shfl(F, lane, -(int)d);
@@ -82,30 +94,23 @@ __device__ __forceinline__ void slab_prefix(typename Op::T (&v)[R], uint32_t m0,
     T c = carry;
     if (lane > 0) c = Fe ? Ve : Op::combine(carry, Ve);
     // elements before the lane's first head extend the carried segment
+    const uint64_t before = heads ? ((1ull << __builtin_ctzll(heads)) - 1ull) : ~0ull;
 #pragma unroll
     for (int e = 0; e < R; ++e)
-        if ((headmask & ((2u << e) - 1u)) == 0u) v[e] = Op::combine(c, v[e]);
+        if ((before >> e) & 1ull) v[e] = Op::combine(c, v[e]);
 }
 
 // In-segment suffix sums of one slab, without the part of the last segment
-// that lies in the next slab (patched by the caller).
+// that lies in the next slab (patched by the caller).  ends: the lane's
+// segment ends.
 template <class Op, int R>
-__device__ __forceinline__ void slab_suffix(typename Op::T (&v)[R], uint32_t m0, uint32_t w,
-                                            uint32_t span, int lane) {
+__device__ __forceinline__ void slab_suffix(typename Op::T (&v)[R], uint64_t ends, uint32_t span,
+                                            int lane) {
     using T = typename Op::T;
-    uint32_t endmask = 0;
-    {
-        uint32_t m = m0;
-#pragma unroll
-        for (int e = 0; e < R; ++e) {
-            endmask |= (m + 1u == w ? 1u : 0u) << e;
-            m = (m + 1u == w) ? 0u : m + 1u;
-        }
-    }
 #pragma unroll
     for (int e = R - 2; e >= 0; --e)
-        if (!((endmask >> e) & 1u)) v[e] = Op::combine(v[e], v[e + 1]);
-    uint32_t G = endmask != 0u;
+        if (!((ends >> e) & 1ull)) v[e] = Op::combine(v[e], v[e + 1]);
+    uint32_t G = ends != 0ull;
     T U = v[0];
     for (uint32_t d = 1; d < span; d <<= 1) {
         const uint32_t Go = shfl(G, lane, (int)d);
@@ -118,9 +123,10 @@ __device__ __forceinline__ void slab_suffix(typename Op::T (&v)[R], uint32_t m0,
     const T Ue = shfl(U, lane, 1);
     if (lane < kWave - 1) {
         // elements after the lane's last segment end continue into lane+1
+        const uint64_t after = ends ? ~((2ull << (63 - __builtin_clzll(ends))) - 1ull) : ~0ull;
 #pragma unroll
         for (int e = 0; e < R; ++e)
-            if ((endmask >> e) == 0u) v[e] = Op::combine(v[e], Ue);
+            if ((after >> e) & 1ull) v[e] = Op::combine(v[e], Ue);
     }
 }
 
