@@ -126,10 +126,13 @@ __device__ __forceinline__ uint64_t revpairs64(uint64_t x) {
 // k-mer values (canonical or forward, hashed or not) of the 16 positions of
 // lane t, from the LDS code/invalid words t, t+1, t+2.  bad: bit e set iff the
 // k-mer at position e covers an invalid base.
-template <bool KM64>
+template <bool KM64, int FLAGS = -1>
 __device__ __forceinline__ void lane_kmers(const uint32_t* s_code, const uint32_t* s_inv, int t,
-                                           uint32_t k, bool canon, bool hashed,
+                                           uint32_t k, bool canon_rt, bool hashed_rt,
                                            uint64_t (&val)[kR], uint32_t& bad) {
+    // FLAGS >= 0 fixes the flags at compile time (bit 0 forward, bit 1 identity)
+    const bool canon = FLAGS >= 0 ? (FLAGS & 1) == 0 : canon_rt;
+    const bool hashed = FLAGS >= 0 ? (FLAGS & 2) == 0 : hashed_rt;
     const uint32_t w0 = s_code[t], w1 = s_code[t + 1], w2 = s_code[t + 2];
     const uint64_t M = (uint64_t)s_inv[t] | ((uint64_t)s_inv[t + 1] << 16) |
                        ((uint64_t)s_inv[t + 2] << 32);
@@ -222,19 +225,30 @@ __device__ __forceinline__ void fetch_words(const GenomeInput& in, int64_t K0, i
     }
 }
 
+// Four ASCII bytes at once: per byte, code = bits 1..2 xor-folded, valid iff
+// the upper-cased byte equals "ACGT"[code] (one byte permute builds the
+// expected bytes).  Returns the 4 codes packed first-base-high in 8 bits and
+// sets bit i of *inv4 for an invalid byte i; invalid bytes get code 0.
+__device__ __forceinline__ uint32_t ascii4(uint32_t x, uint32_t* inv4) {
+    const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    const uint32_t expect = __builtin_amdgcn_perm(0u, 0x54474341u, c);  // 'T' 'G' 'C' 'A'
+    const uint32_t d = (x & 0xDFDFDFDFu) ^ expect;
+    const uint32_t nz = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;  // byte != 0
+    const uint32_t bad = nz >> 7;                                              // 0 or 1 per byte
+    const uint32_t cv = c & ~(bad * 3u);                                       // invalid -> code 0
+    const uint32_t t = bad | (bad >> 7);
+    *inv4 = (t | (t >> 14)) & 0xFu;
+    return ((cv & 3u) << 6) | ((cv >> 4) & 0x30u) | ((cv >> 14) & 0xCu) | (cv >> 24);
+}
+
 __device__ __forceinline__ void ascii_word(const GenomeInput& in, int64_t base, const uint4& q,
                                            uint32_t& code, uint32_t& inv) {
     if (in.aligned && base >= 0 && (uint64_t)base + 16 <= in.n) {
-        const uint32_t word[4] = {q.x, q.y, q.z, q.w};
-        code = 0;
-        inv = 0;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const uint32_t b = (word[i >> 2] >> (8 * (i & 3))) & 0xFFu;
-            const bool ok = base_valid(b);
-            code |= (ok ? base_code(b) : 0u) << (30 - 2 * i);
-            inv |= (ok ? 0u : 1u) << i;
-        }
+        uint32_t i0, i1, i2, i3;
+        const uint32_t b0 = ascii4(q.x, &i0), b1 = ascii4(q.y, &i1);
+        const uint32_t b2 = ascii4(q.z, &i2), b3 = ascii4(q.w, &i3);
+        code = (b0 << 24) | (b1 << 16) | (b2 << 8) | b3;
+        inv = i0 | (i1 << 4) | (i2 << 8) | (i3 << 12);
     } else {
         ascii16(in.seq, base, in.n, false, code, inv);  // edges and unaligned input
     }
@@ -587,27 +601,60 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
 // ---------------------------------------------------------------------------
 constexpr int kWaveKeys = kWave * kR;  // 1024 keys per wave tile
 constexpr int kWaveWords = kWaveKeys / 16 + 2;
-constexpr int kWaveSlots = kWaveKeys + 2 * kWave;  // keys + room for dumped lanes
 
 template <bool FULL>
 __device__ __forceinline__ Key key_min(const Key& l, const Key& r) {
     return OpKeyMin<FULL>::combine(l, r);
 }
 
-template <int NT, int IN, bool KM64, bool FULL>
+// One doubling step in registers: m[e] = min(m[e], m[e + S]); a lane reads
+// m[e + S] past its run from the next lane (values taken before any update).
+template <int S, bool FULL>
+__device__ __forceinline__ void doubling_step(Key (&m)[kR], int lane) {
+    Key nb[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) nb[t] = shfl(m[t], lane, 1);
+#pragma unroll
+    for (int e = 0; e < kR; ++e) {
+        const Key r = (e + S < kR) ? m[e + S] : nb[e + S - kR];
+        m[e] = key_min<FULL>(m[e], r);
+    }
+}
+
+// The last step shifts by w - 2^L, known only at run time: a uniform switch
+// over the 15 possible values keeps every register index static.
+template <bool FULL>
+__device__ __forceinline__ void doubling_shift(Key (&m)[kR], int lane, uint32_t shift) {
+    switch (shift) {
+    case 1: doubling_step<1, FULL>(m, lane); break;
+    case 2: doubling_step<2, FULL>(m, lane); break;
+    case 3: doubling_step<3, FULL>(m, lane); break;
+    case 4: doubling_step<4, FULL>(m, lane); break;
+    case 5: doubling_step<5, FULL>(m, lane); break;
+    case 6: doubling_step<6, FULL>(m, lane); break;
+    case 7: doubling_step<7, FULL>(m, lane); break;
+    case 8: doubling_step<8, FULL>(m, lane); break;
+    case 9: doubling_step<9, FULL>(m, lane); break;
+    case 10: doubling_step<10, FULL>(m, lane); break;
+    case 11: doubling_step<11, FULL>(m, lane); break;
+    case 12: doubling_step<12, FULL>(m, lane); break;
+    case 13: doubling_step<13, FULL>(m, lane); break;
+    case 14: doubling_step<14, FULL>(m, lane); break;
+    case 15: doubling_step<15, FULL>(m, lane); break;
+    default: break;
+    }
+}
+
+template <int NT, int IN, bool KM64, bool FULL, int FLAGS>
 __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, MinimizerArgs a) {
     constexpr int NWV = NT / kWave;
     __shared__ uint32_t s_code[NWV][kWaveWords], s_inv[NWV][kWaveWords];
-    __shared__ uint64_t s_h[NWV][kWaveSlots + kWaveSlots / 16];
-    __shared__ uint16_t s_tag[NWV][kWaveSlots + kWaveSlots / 16];
 
     const int lane = lane_id();
     const int wv = (int)(threadIdx.x >> 6);
     const uint32_t w = a.w;
     uint32_t* code = s_code[wv];
     uint32_t* inv = s_inv[wv];
-    uint64_t* sh = s_h[wv];
-    uint16_t* stag = s_tag[wv];
 
     // Tile order = workgroup order.  A tile waits (look-back) only for tiles
     // of lower index, which belong to workgroups dispatched before it; the
@@ -629,8 +676,8 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
         {
             uint64_t val[kR];
             uint32_t bad;
-            lane_kmers<KM64>(code, inv, lane, a.k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u,
-                             val, bad);
+            lane_kmers<KM64, FLAGS>(code, inv, lane, a.k, (a.flags & 1u) == 0u,
+                                    (a.flags & 2u) == 0u, val, bad);
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
                 const bool iv = (bad >> e) & 1u;
@@ -640,50 +687,15 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
             }
         }
 
-        // 3. window minimum by doubling: levels 1, 2, 4, 8, 16 while 2s <= w
+        // 3. window minimum by doubling: levels 1, 2, 4, 8, 16 while 2s <= w,
+        //    then one step by w - 2^L
         uint32_t L = 1;
-#pragma unroll
-        for (int s = 1; s <= 16; s *= 2) {
-            if ((uint32_t)(2 * s) <= w) {
-                Key nb[16];
-#pragma unroll
-                for (int t = 0; t < s; ++t) nb[t] = shfl(m[t], lane, 1);
-#pragma unroll
-                for (int e = 0; e < kR; ++e) {
-                    const Key r = (e + s < kR) ? m[e + s] : nb[e + s - kR];
-                    m[e] = key_min<FULL>(m[e], r);
-                }
-                L = 2u * (uint32_t)s;
-            }
-        }
-        const uint32_t shift = w - L;  // 0 <= shift < L <= 16
-        if (shift != 0u) {
-#pragma unroll
-            for (int e = 0; e < kR; ++e) {
-                const uint32_t j = (uint32_t)lane * kR + e;
-                sh[pad16(j)] = ((uint64_t)m[e].hi << 32) | m[e].lo;
-                stag[pad16(j)] = (uint16_t)m[e].tag;
-            }
-            if (lane < 1) {  // keys past the tile read as invalid
-#pragma unroll
-                for (int e = 0; e < kR; ++e) {
-                    sh[pad16(kWaveKeys + e)] = ~0ull;
-                    stag[pad16(kWaveKeys + e)] = 0xFFFFu;
-                }
-            }
-            wave_lds_sync();
-#pragma unroll
-            for (int e = 0; e < kR; ++e) {
-                const uint32_t q = (uint32_t)lane * kR + e + shift;
-                Key r;
-                const uint64_t h = sh[pad16(q)];
-                r.lo = (uint32_t)h;
-                r.hi = (uint32_t)(h >> 32);
-                r.tag = stag[pad16(q)];
-                m[e] = key_min<FULL>(m[e], r);
-            }
-            wave_lds_sync();
-        }
+        if (2u <= w) { doubling_step<1, FULL>(m, lane); L = 2; }
+        if (4u <= w) { doubling_step<2, FULL>(m, lane); L = 4; }
+        if (8u <= w) { doubling_step<4, FULL>(m, lane); L = 8; }
+        if (16u <= w) { doubling_step<8, FULL>(m, lane); L = 16; }
+        if (32u <= w) { doubling_step<16, FULL>(m, lane); L = 32; }
+        doubling_shift<FULL>(m, lane, w - L);  // 0 <= w - L < L <= 32
 
         // 4. dedup: window j is stored iff owned, valid and at a new position
         uint32_t emit = 0;
@@ -701,7 +713,7 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
             }
         }
 
-        // 5. ordered compaction: lane prefix, look-back, staged coalesced stores
+        // 5. ordered compaction: lane prefix, look-back, stores from registers
         const uint32_t cnt = (uint32_t)__builtin_popcount(emit);
         uint32_t incl = cnt;
 #pragma unroll
@@ -710,23 +722,16 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
             if (lane >= d) incl += o;
         }
         const uint32_t total = lane_value(incl, kWave - 1);
-        uint32_t slot = incl - cnt;
+        const uint64_t excl = tile_lookback(a.status, cur, total, a.err, lane);
+        uint64_t g = excl + (incl - cnt);
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
-            const bool on = (emit >> e) & 1u;
-            // lanes with nothing to store write into their own dump slot
-            const uint32_t at = on ? slot : (uint32_t)(kWaveKeys + kWave + lane);
-            sh[at] = ((uint64_t)m[e].hi << 32) | m[e].lo;
-            stag[at] = (uint16_t)(m[e].tag & 0x7FFFu);
-            slot += on ? 1u : 0u;
-        }
-        const uint64_t excl = tile_lookback(a.status, cur, total, a.err, lane);
-        wave_lds_sync();
-        for (uint32_t i = (uint32_t)lane; i < total; i += kWave) {
-            const uint64_t g = excl + i;
-            if (g < a.capacity) {
-                a.out_hash[g] = sh[i];
-                a.out_pos[g] = (uint32_t)(K0 + (int64_t)stag[i]);
+            if ((emit >> e) & 1u) {
+                if (g < a.capacity) {
+                    a.out_hash[g] = ((uint64_t)m[e].hi << 32) | m[e].lo;
+                    a.out_pos[g] = (uint32_t)(K0 + (int64_t)(m[e].tag & 0x7FFFu));
+                }
+                ++g;
             }
         }
         if (lane == 0 && cur == a.ntiles - 1) *a.d_count = final_count(a.err, excl + total);
@@ -800,8 +805,13 @@ template <int NT, int IN, bool KM64, bool FULL>
 static void launch_wave_variant(const GenomeInput& in, const MinimizerArgs& a, hipStream_t s) {
     constexpr int NWV = NT / kWave;
     const unsigned grid = (unsigned)((a.ntiles + NWV - 1) / NWV);
-    hipLaunchKernelGGL((minimizer_wave_kernel<NT, IN, KM64, FULL>), dim3(grid), dim3(NT), 0, s,
-                       in, a);
+    // canonical + hashed (flags 0) is compiled with the flags fixed
+    if (a.flags == 0u)
+        hipLaunchKernelGGL((minimizer_wave_kernel<NT, IN, KM64, FULL, 0>), dim3(grid), dim3(NT), 0,
+                           s, in, a);
+    else
+        hipLaunchKernelGGL((minimizer_wave_kernel<NT, IN, KM64, FULL, -1>), dim3(grid), dim3(NT),
+                           0, s, in, a);
 }
 
 template <int NT, int IN>
