@@ -185,14 +185,28 @@ int sws_minimizers_2bit(const uint32_t* packed, const uint32_t* invalid, uint64_
                              ws_bytes, s);
 }
 
+// Batched calls need w <= 32 (one wavefront's tile) and k + w <= 49 (the
+// boundary bits a lane tests fit in 64).
+int check_batch_args(uint64_t total, uint32_t k, uint32_t w, uint32_t flags) {
+    if (k < 1 || k > 31 || w < 1 || !known_flags(flags)) return SWS_ERR_INVALID;
+    if (w > 32 || k + w > 49) return SWS_ERR_UNSUPPORTED;
+    if (total >= kMaxPositions) return SWS_ERR_UNSUPPORTED;
+    return SWS_OK;
+}
+
+uint64_t batch_tiles(uint64_t total, uint32_t w) {
+    const uint32_t tw = sws::batch_tile_windows(w);
+    return total ? (total + tw - 1) / tw : 0;
+}
+
 int sws_minimizers_batch_workspace(uint64_t total_bases, uint32_t nreads, uint32_t k, uint32_t w,
                                    uint64_t* bytes) {
-    (void)total_bases;
     (void)nreads;
-    (void)k;
-    (void)w;
     if (bytes == nullptr) return SWS_ERR_INVALID;
-    return SWS_ERR_UNSUPPORTED;
+    const int st = check_batch_args(total_bases, k, w, 0);
+    if (st != SWS_OK) return st;
+    *bytes = sws::batch_workspace_bytes(batch_tiles(total_bases, w));
+    return SWS_OK;
 }
 
 int sws_minimizers_batch(const uint8_t* seqs, const uint64_t* d_offsets, uint32_t nreads,
@@ -200,14 +214,49 @@ int sws_minimizers_batch(const uint8_t* seqs, const uint64_t* d_offsets, uint32_
                          uint64_t* out_hash, uint32_t* out_pos, uint32_t* out_read,
                          uint64_t capacity, uint64_t* d_read_out_offsets, void* workspace,
                          uint64_t ws_bytes, hipStream_t s) {
-    (void)seqs; (void)d_offsets; (void)nreads; (void)total_bases; (void)k; (void)w; (void)flags;
-    (void)out_hash; (void)out_pos; (void)out_read; (void)capacity; (void)d_read_out_offsets;
-    (void)workspace; (void)ws_bytes; (void)s;
-    return SWS_ERR_UNSUPPORTED;
+    const int st = check_batch_args(total_bases, k, w, flags);
+    if (st != SWS_OK) return st;
+    if (d_offsets == nullptr || d_read_out_offsets == nullptr) return SWS_ERR_INVALID;
+    if (total_bases > 0 && seqs == nullptr) return SWS_ERR_INVALID;
+    if (capacity > 0 && (out_hash == nullptr || out_pos == nullptr || out_read == nullptr))
+        return SWS_ERR_INVALID;
+    const uint64_t ntiles = batch_tiles(total_bases, w);
+    const uint64_t need = sws::batch_workspace_bytes(ntiles);
+    if (workspace == nullptr || ws_bytes < need || ((uintptr_t)workspace & 7u)) return SWS_ERR_WORKSPACE;
+    if (ntiles == 0) {
+        // every read is empty: all offsets are 0
+        return sws::launch_zero(d_read_out_offsets, (uint64_t)nreads + 1, s) == 0 ? SWS_OK
+                                                                                 : SWS_ERR_DEVICE;
+    }
+    sws::GenomeInput in;
+    memset(&in, 0, sizeof(in));
+    in.kind = sws::kInAscii;
+    in.aligned = ((uintptr_t)seqs & 15u) == 0;
+    in.seq = seqs;
+    in.n = total_bases;
+    sws::BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.offsets = d_offsets;
+    a.nreads = nreads;
+    a.total = total_bases;
+    a.k = k;
+    a.w = w;
+    a.flags = flags;
+    a.tw = sws::batch_tile_windows(w);
+    a.ntiles = ntiles;
+    a.out_hash = out_hash;
+    a.out_pos = out_pos;
+    a.out_read = out_read;
+    a.capacity = capacity;
+    a.read_out = d_read_out_offsets;
+    const uint32_t nt = g_min_block[bucket_of(total_bases, nreads)];
+    return sws::launch_minimizers_batch(in, a, nt > 256 ? 256 : nt, workspace, s) == 0
+               ? SWS_OK : SWS_ERR_DEVICE;
 }
 
 int sws_set_minimizer_block(uint32_t bucket, uint32_t threads) {
-    if (bucket > 2 || (threads != 128 && threads != 256 && threads != 512)) return SWS_ERR_INVALID;
+    if (bucket > 2 || (threads != 64 && threads != 128 && threads != 256 && threads != 512))
+        return SWS_ERR_INVALID;
     g_min_block[bucket] = threads;
     return SWS_OK;
 }

@@ -738,6 +738,218 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batched minimizers: many reads of uneven length, one launch.
+//
+// The reads are concatenated; every base position p is a candidate window.
+// Window p belongs to the read containing p and exists iff it ends inside that
+// read (p + w + k - 1 <= read end); a k-mer exists iff it ends inside its read
+// and covers no invalid base; dedup restarts at each read start.  Tiles are
+// the single-sequence wavefront tiles over the concatenation.  A tile learns
+// the read boundaries it overlaps as a bitmap of read starts in LDS (plus a
+// rank -> (read, start) table), and tests "does a read start inside (i, i+L]"
+// with the same OR-by-doubling used for invalid bases.  Outputs are read-major
+// because the concatenation is; the tile that owns a read's start position
+// writes that read's output offset.
+// ---------------------------------------------------------------------------
+constexpr int kTileRange = kWaveKeys + 64;   // positions whose boundaries a tile needs
+constexpr int kBitmapWords = kTileRange / 32 + 2;
+
+// Read containing the first base of each tile: a read covering tiles whose
+// first base (q * tw - 16, clamped at 0) lies in it writes its index there.
+__global__ void batch_first_read_kernel(const uint64_t* __restrict__ offsets, uint32_t nreads,
+                                        uint32_t tw, uint64_t ntiles,
+                                        uint32_t* __restrict__ first_read) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nreads;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t s = offsets[r], e = offsets[r + 1];
+        if (e <= s) continue;
+        const uint64_t qa = s == 0 ? 0 : (s + 16 + tw - 1) / tw;
+        uint64_t qb = (e + 16 + tw - 1) / tw;
+        if (qb > ntiles) qb = ntiles;
+        for (uint64_t q = qa; q < qb; ++q) first_read[q] = (uint32_t)r;
+    }
+}
+
+// OR over the `len` bits following each of bits 0..15: bit e of the result is
+// set iff some bit in [e+1, e+len] of x is.  len <= 62 - 15.
+__device__ __forceinline__ uint32_t or_after(uint64_t x, uint32_t len) {
+    if (len == 0) return 0;
+    uint64_t A = x >> 1;
+    uint32_t l = 1;
+    while (2u * l <= len) {
+        A |= A >> l;
+        l *= 2u;
+    }
+    return (uint32_t)((A | (A >> (len - l))) & 0xFFFFu);
+}
+
+template <int NT, bool KM64, bool FULL, int FLAGS>
+__global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, BatchArgs a) {
+    constexpr int NWV = NT / kWave;
+    __shared__ uint32_t s_code[NWV][kWaveWords], s_inv[NWV][kWaveWords];
+    __shared__ uint32_t s_bits[NWV][kBitmapWords];
+    __shared__ uint32_t s_rid[NWV][kTileRange + 1];
+    __shared__ uint32_t s_rstart[NWV][kTileRange + 1];
+    __shared__ uint32_t s_lexcl[NWV][kWave], s_lemit[NWV][kWave];
+
+    const int lane = lane_id();
+    const int wv = (int)(threadIdx.x >> 6);
+    const uint32_t w = a.w, k = a.k;
+    uint32_t* code = s_code[wv];
+    uint32_t* inv = s_inv[wv];
+    uint32_t* bits = s_bits[wv];
+    uint32_t* rid = s_rid[wv];
+    uint32_t* rstart = s_rstart[wv];
+
+    const uint64_t cur = (uint64_t)blockIdx.x * NWV + (uint64_t)wv;
+    if (cur >= a.ntiles) return;
+    const int64_t p0 = (int64_t)(cur * a.tw);
+    const int64_t K0 = p0 - 16;
+    RawWords raw;
+    fetch_words<kInAscii>(in, K0, lane, raw);
+
+    // read boundaries of [K0, K0 + kTileRange)
+    for (int i = lane; i < kBitmapWords; i += kWave) bits[i] = 0u;
+    wave_lds_sync();
+    const int64_t rng_end = K0 + kTileRange;
+    const uint32_t r0 = a.first_read[cur];
+    uint32_t listed = 0;
+    uint32_t pre = 0;  // the first listed read starts before the tile
+    for (uint64_t base_r = r0;; base_r += kWave) {
+        const uint64_t r = base_r + (uint64_t)lane;
+        const bool have = r < a.nreads;
+        const int64_t rs = have ? (int64_t)a.offsets[r] : (int64_t)a.total;
+        const int64_t re = have ? (int64_t)a.offsets[r + 1] : (int64_t)a.total;
+        const bool take = have && re > rs && re > K0 && rs < rng_end;
+        const uint64_t tmask = __ballot(take);
+        if (take) {
+            const uint32_t idx = listed + (uint32_t)__builtin_popcountll(tmask & ((1ull << lane) - 1ull));
+            if (idx <= (uint32_t)kTileRange) {
+                rid[idx] = (uint32_t)r;
+                rstart[idx] = (uint32_t)rs;
+            }
+            if (rs >= K0) {
+                const uint32_t b = (uint32_t)(rs - K0);
+                atomicOr(&bits[b >> 5], 1u << (b & 31));
+            } else {
+                pre = 1;
+            }
+        }
+        listed += (uint32_t)__builtin_popcountll(tmask);
+        if (__ballot(!have || rs >= rng_end)) break;
+    }
+    pre = __ballot(pre != 0) ? 1u : 0u;
+    if (lane == 0 && (int64_t)a.total >= K0 && (int64_t)a.total < rng_end) {
+        const uint32_t b = (uint32_t)((int64_t)a.total - K0);  // end of the last read
+        atomicOr(&bits[b >> 5], 1u << (b & 31));
+    }
+    wave_lds_sync();
+    // this lane's 64 boundary bits from tile position 16 * lane
+    uint64_t B;
+    {
+        const uint32_t wi = (uint32_t)lane >> 1;
+        const uint64_t W = (uint64_t)bits[wi] | ((uint64_t)bits[wi + 1] << 32);
+        B = (lane & 1) ? ((W >> 16) | ((uint64_t)bits[wi + 2] << 48)) : W;
+    }
+    const uint32_t kcross = or_after(B, k - 1u);      // k-mer e spans a read start
+    const uint32_t wcross = or_after(B, k + w - 2u);  // window e spans a read start
+
+    // bases and keys
+    commit_words<kInAscii>(in, K0, lane, raw, code, inv);
+    wave_lds_sync();
+    Key m[kR];
+    {
+        uint64_t val[kR];
+        uint32_t bad;
+        lane_kmers<KM64, FLAGS>(code, inv, lane, k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u,
+                                val, bad);
+        bad |= kcross;
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const bool iv = (bad >> e) & 1u;
+            m[e].lo = iv ? 0xFFFFFFFFu : (uint32_t)val[e];
+            m[e].hi = iv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
+            m[e].tag = ((uint32_t)lane * kR + e) | (iv ? kInvalidTag : 0u);
+        }
+    }
+    uint32_t L = 1;
+    if (2u <= w) { doubling_step<1, FULL>(m, lane); L = 2; }
+    if (4u <= w) { doubling_step<2, FULL>(m, lane); L = 4; }
+    if (8u <= w) { doubling_step<4, FULL>(m, lane); L = 8; }
+    if (16u <= w) { doubling_step<8, FULL>(m, lane); L = 16; }
+    if (32u <= w) { doubling_step<16, FULL>(m, lane); L = 32; }
+    doubling_shift<FULL>(m, lane, w - L);
+
+    // dedup, restarting at read starts
+    uint32_t emit = 0;
+    {
+        uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
+#pragma unroll
+        for (int e = 0; e < kR; ++e) {
+            const uint32_t j = (uint32_t)lane * kR + e;
+            const int64_t p = K0 + (int64_t)j;
+            const bool owned = j >= 16u && j < 16u + a.tw && p < (int64_t)a.total;
+            const bool valid = (m[e].tag & kInvalidTag) == 0u && !((wcross >> e) & 1u);
+            const bool fresh = ((B >> e) & 1u) || m[e].tag != prev;
+            emit |= (owned && valid && fresh ? 1u : 0u) << e;
+            prev = m[e].tag;
+        }
+    }
+    const uint32_t cnt = (uint32_t)__builtin_popcount(emit);
+    const uint32_t starts = (uint32_t)__builtin_popcountll(B & 0xFFFFull);
+    uint32_t incl = cnt, sincl = starts;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = shfl(incl, lane, -d);
+        const uint32_t so = shfl(sincl, lane, -d);
+        if (lane >= d) {
+            incl += o;
+            sincl += so;
+        }
+    }
+    const uint32_t total = lane_value(incl, kWave - 1);
+    s_lexcl[wv][lane] = incl - cnt;
+    s_lemit[wv][lane] = emit;
+    const uint64_t excl = tile_lookback(a.status, cur, total, a.err, lane);
+    // read rank of position e: listed reads starting at or before it, minus one
+    const int32_t rank0 = (int32_t)(pre + sincl - starts) - 1;
+    uint64_t g = excl + (incl - cnt);
+#pragma unroll
+    for (int e = 0; e < kR; ++e) {
+        if ((emit >> e) & 1u) {
+            if (g < a.capacity) {
+                const int32_t rk = rank0 + __builtin_popcountll(B & ((2ull << e) - 1ull));
+                const uint32_t rr = rid[rk];
+                a.out_hash[g] = ((uint64_t)m[e].hi << 32) | m[e].lo;
+                a.out_pos[g] = (uint32_t)(K0 + (int64_t)(m[e].tag & 0x7FFFu)) - rstart[rk];
+                a.out_read[g] = rr;
+            }
+            ++g;
+        }
+    }
+    wave_lds_sync();
+    // output offsets of the reads that start in the windows this tile owns
+    const bool last = cur == a.ntiles - 1;
+    const int64_t own_end = last ? INT64_MAX : p0 + (int64_t)a.tw;
+    for (uint64_t base_r = r0;; base_r += kWave) {
+        const uint64_t r = base_r + (uint64_t)lane;
+        const bool have = r < a.nreads;
+        const int64_t rs = have ? (int64_t)a.offsets[r] : INT64_MAX;
+        if (have && rs >= p0 && rs < own_end) {
+            const int64_t j = rs - K0;
+            uint32_t before = total;
+            if (j < 16 + (int64_t)a.tw) {
+                const uint32_t l = (uint32_t)(j >> 4), e = (uint32_t)(j & 15);
+                before = s_lexcl[wv][l] + (uint32_t)__builtin_popcount(s_lemit[wv][l] & ((1u << e) - 1u));
+            }
+            a.read_out[r] = excl + before;
+        }
+        if (__ballot(!have || rs >= own_end)) break;
+    }
+    if (last && lane == 0) a.read_out[a.nreads] = final_count(a.err, excl + total);
+}
+
 __global__ void zero_words_kernel(uint64_t* __restrict__ p, uint64_t count) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -783,6 +995,51 @@ int launch_kmers(const GenomeInput& in, uint32_t k, uint32_t flags, uint64_t* ou
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+
+template <int NT, bool KM64, bool FULL>
+static void launch_batch_variant(const GenomeInput& in, const BatchArgs& a, hipStream_t s) {
+    constexpr int NWV = NT / kWave;
+    const unsigned grid = (unsigned)((a.ntiles + NWV - 1) / NWV);
+    if (a.flags == 0u)
+        hipLaunchKernelGGL((minimizer_batch_kernel<NT, KM64, FULL, 0>), dim3(grid), dim3(NT), 0, s,
+                           in, a);
+    else
+        hipLaunchKernelGGL((minimizer_batch_kernel<NT, KM64, FULL, -1>), dim3(grid), dim3(NT), 0,
+                           s, in, a);
+}
+
+int launch_minimizers_batch(const GenomeInput& in, BatchArgs a, uint32_t nt, void* workspace,
+                            hipStream_t s) {
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    a.err = reinterpret_cast<uint32_t*>(ws + 8);
+    a.status = reinterpret_cast<uint64_t*>(ws + kWsStatusOffset);
+    a.first_read = reinterpret_cast<uint32_t*>(ws + kWsStatusOffset + 8 * a.ntiles);
+    if (launch_zero(reinterpret_cast<uint64_t*>(ws), kWsStatusOffset / 8 + a.ntiles, s) != 0)
+        return -1;
+    const uint64_t rb = ((uint64_t)a.nreads + 255) / 256;
+    hipLaunchKernelGGL(batch_first_read_kernel, dim3((unsigned)(rb < 4096 ? (rb ? rb : 1) : 4096)),
+                       dim3(256), 0, s, a.offsets, a.nreads, a.tw, a.ntiles, a.first_read);
+    const bool km64 = a.k > 16;
+    const bool full = a.k >= 30 && (a.flags & 2u) == 0u;
+    if (nt == 128) {
+        if (!km64) launch_batch_variant<128, false, false>(in, a, s);
+        else if (!full) launch_batch_variant<128, true, false>(in, a, s);
+        else launch_batch_variant<128, true, true>(in, a, s);
+    } else if (nt == 64) {
+        if (!km64) launch_batch_variant<64, false, false>(in, a, s);
+        else if (!full) launch_batch_variant<64, true, false>(in, a, s);
+        else launch_batch_variant<64, true, true>(in, a, s);
+    } else {
+        if (!km64) launch_batch_variant<256, false, false>(in, a, s);
+        else if (!full) launch_batch_variant<256, true, false>(in, a, s);
+        else launch_batch_variant<256, true, true>(in, a, s);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+uint64_t batch_workspace_bytes(uint64_t ntiles) { return kWsStatusOffset + 12ull * ntiles; }
+
+uint32_t batch_tile_windows(uint32_t w) { return minimizer_tile_windows(kWave, w); }
 
 uint32_t minimizer_tile_windows(uint32_t nt, uint32_t w) {
     const uint32_t P = nt * kR;

@@ -43,7 +43,27 @@ struct MinimizerArgs {
     uint64_t* status;
 };
 
+struct BatchArgs {
+    const uint64_t* offsets;  // nreads + 1
+    uint32_t nreads;
+    uint64_t total;           // bases in the batch
+    uint32_t k, w, flags, tw;
+    uint64_t ntiles;
+    uint64_t* out_hash;
+    uint32_t* out_pos;
+    uint32_t* out_read;
+    uint64_t capacity;
+    uint64_t* read_out;       // nreads + 1
+    uint32_t* first_read;     // workspace: per tile
+    uint64_t* status;         // workspace
+    uint32_t* err;            // workspace
+};
+
 int launch_zero(uint64_t* p, uint64_t words, hipStream_t s);
+int launch_minimizers_batch(const GenomeInput& in, BatchArgs a, uint32_t nt, void* workspace,
+                            hipStream_t s);
+uint64_t batch_workspace_bytes(uint64_t ntiles);
+uint32_t batch_tile_windows(uint32_t w);
 int launch_pack2bit(const uint8_t* seq, uint64_t n, uint32_t* packed, uint32_t* invalid,
                     hipStream_t s);
 int launch_kmers(const GenomeInput& in, uint32_t k, uint32_t flags, uint64_t* out, hipStream_t s);

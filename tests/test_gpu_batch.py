@@ -1,0 +1,117 @@
+"""Batched minimizers (many uneven reads, one launch) against the oracle run
+read by read.  Bit-exact, including per-read output offsets."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import host_u32, host_u64, torch_cuda
+from paper_1811_10074_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def make_batch(lens, seed, n_rate=0.02, lower=0.02):
+    lens = np.asarray(lens, dtype=np.int64)
+    off = np.zeros(lens.size + 1, dtype=np.uint64)
+    np.cumsum(lens, out=off[1:])
+    seqs = inputs.dna(int(off[-1]), seed=seed, n_rate=n_rate, lowercase_rate=lower)
+    return seqs, off
+
+
+def check_batch(torch, seqs, off, k, w, canonical=True, hashed=True, tag=""):
+    from paper_1811_10074_amd import batch
+    h, p, r, ro = batch.minimizers_batch(torch.from_numpy(seqs).cuda(), off, k, w, canonical, hashed)
+    torch.cuda.synchronize()
+    eh, ep, er, ero = oracle.minimizers_batch(seqs, off, k, w, canonical, hashed)
+    assert np.array_equal(ro.cpu().numpy().view(np.uint64), ero), tag
+    assert np.array_equal(host_u32(r), er), tag
+    assert np.array_equal(host_u32(p), ep), tag
+    assert np.array_equal(host_u64(h), eh), tag
+
+
+@pytest.mark.parametrize("k,w", [(15, 10), (19, 19), (3, 3), (1, 1), (5, 2), (21, 28), (16, 32),
+                                 (31, 18)])
+def test_random_batches(k, w):
+    torch = torch_cuda()
+    rng = np.random.default_rng(k * 100 + w)
+    for trial in range(3):
+        lens = rng.integers(0, 400, 300)
+        lens[rng.random(300) < 0.1] = 0
+        seqs, off = make_batch(lens, seed=trial + 7 * k + w)
+        check_batch(torch, seqs, off, k, w, tag="random %d" % trial)
+    seqs, off = make_batch(rng.integers(0, 3000, 40), seed=99)
+    for can in (True, False):
+        for hsh in (True, False):
+            check_batch(torch, seqs, off, k, w, can, hsh, tag="flags")
+
+
+def test_edges():
+    torch = torch_cuda()
+    k, w = 15, 10
+    cases = {
+        "all empty": [0, 0, 0],
+        "one empty": [0],
+        "too short": [k + w - 2] * 50,
+        "exact": [k + w - 1] * 50,
+        "tiny many": list(np.random.default_rng(1).integers(0, 6, 5000)),
+        "trailing empty": [500, 700, 0, 0],
+        "leading empty": [0, 0, 800, 3],
+        "one long": [200_000],
+        "alternating": [1, 3000] * 40,
+    }
+    for name, lens in cases.items():
+        seqs, off = make_batch(lens, seed=len(name))
+        check_batch(torch, seqs, off, k, w, tag=name)
+    # tiny reads with k = w = 1: every base is a window, up to a thousand reads per tile
+    seqs, off = make_batch(np.random.default_rng(2).integers(0, 4, 20000), seed=3, n_rate=0.1)
+    check_batch(torch, seqs, off, 1, 1, tag="k=w=1 tiny")
+
+
+def test_matches_single_sequence():
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    seqs, off = make_batch([300_001], seed=11, n_rate=0.01)
+    from paper_1811_10074_amd import batch
+    h, p, r, ro = batch.minimizers_batch(torch.from_numpy(seqs).cuda(), off, 15, 10)
+    hs, ps = sws.minimizers(torch.from_numpy(seqs).cuda(), 15, 10)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u64(h), host_u64(hs)) and np.array_equal(host_u32(p), host_u32(ps))
+
+
+def test_unsupported():
+    torch = torch_cuda()
+    from paper_1811_10074_amd import batch
+    seqs, off = make_batch([100, 200], seed=1)
+    with pytest.raises(ValueError):
+        batch.minimizers_batch(torch.from_numpy(seqs).cuda(), off, 31, 19)
+    with pytest.raises(ValueError):
+        batch.minimizers_batch(torch.from_numpy(seqs).cuda(), off, 15, 33)
+
+
+def test_config4_subsample_bucketed_graph():
+    """A subsample of the uneven-read workload (150-b reads plus lognormal
+    long reads, 1% N), split into length buckets with tuned block sizes and
+    captured in one HIP graph: every replay equals the oracle, read by read."""
+    torch = torch_cuda()
+    from paper_1811_10074_amd import batch, tune
+    seqs, off = inputs.read_batch(n_short=20_000, n_long=300, seed=3)
+    table, timings = tune.tune(seqs, off, 15, 10, reps=2)
+    assert set(table) <= {0, 1, 2} and all(t in tune.CANDIDATES for t in table.values())
+    bb = batch.BucketedBatch(seqs, off, 15, 10, tune_table=table)
+    bb.capture()
+    eh, ep, er, ero = oracle.minimizers_batch(seqs, off, 15, 10)
+    rng = np.random.default_rng(0)
+    sample = rng.choice(off.size - 1, 300, replace=False)
+    for rep in range(3):
+        # eager work between replays
+        junk = torch.arange(1 << 20, device="cuda").sum()
+        bb.replay()
+        torch.cuda.synchronize()
+        res = bb.results()
+        total = sum(int(v[3][-1].item()) for v in res.values())
+        assert total == int(ero[-1]), rep
+        for r in sample.tolist():
+            h, p = bb.read_result(r, res)
+            a, e = int(ero[r]), int(ero[r + 1])
+            assert np.array_equal(p, ep[a:e]) and np.array_equal(h, eh[a:e]), (rep, r)
+        del junk
