@@ -1,0 +1,495 @@
+"""Continuous-batching server for minimizer sketching requests.
+
+A request is a set of reads (CSR: bases + offsets).  The scheduler thread
+
+1. admits queued requests, oldest first, while the device arena has room for
+   the batch they form (inputs, outputs at their exact bound, workspace);
+   a request larger than the whole arena is rejected;
+2. packs the admitted requests into one CSR batch, copies it to its arena slot
+   and launches one batched minimizer call on one of several streams;
+3. polls the in-flight batches; a finished batch is copied back, split per
+   request, and its futures resolved; its arena slot is freed.
+
+Requests that arrive while batches run are admitted as soon as memory and a
+stream free up, so their work overlaps on the device.  Every request's result
+is the same alone or in any mix: a batch is a concatenation of independent
+reads and the kernel never lets a window or a k-mer cross a read boundary.
+
+``Executor`` separates the device work from the scheduling: ``GPUExecutor``
+runs libsws; ``FakeExecutor`` (tests) computes on the CPU with configurable
+latency and injected failures.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures
+import ctypes
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import _lib
+
+
+# ---------------------------------------------------------------------------
+# Device arena: first-fit free list over one allocation, with coalescing.
+# ---------------------------------------------------------------------------
+class Arena:
+    ALIGN = 256
+
+    def __init__(self, nbytes: int):
+        self.size = int(nbytes)
+        self.free_list = [(0, self.size)]  # sorted (offset, length)
+        self.used = 0
+
+    @classmethod
+    def round(cls, n: int) -> int:
+        return (int(n) + cls.ALIGN - 1) // cls.ALIGN * cls.ALIGN
+
+    def alloc(self, nbytes: int) -> Optional[int]:
+        n = self.round(max(nbytes, 1))
+        for i, (off, ln) in enumerate(self.free_list):
+            if ln >= n:
+                if ln == n:
+                    self.free_list.pop(i)
+                else:
+                    self.free_list[i] = (off + n, ln - n)
+                self.used += n
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int) -> None:
+        n = self.round(max(nbytes, 1))
+        self.used -= n
+        fl = self.free_list
+        fl.append((off, n))
+        fl.sort()
+        merged = [fl[0]]
+        for o, ln in fl[1:]:
+            po, pl = merged[-1]
+            if po + pl == o:
+                merged[-1] = (po, pl + ln)
+            else:
+                merged.append((o, ln))
+        self.free_list = merged
+
+    @property
+    def free_bytes(self) -> int:
+        return self.size - self.used
+
+
+# ---------------------------------------------------------------------------
+# Requests and batches.
+# ---------------------------------------------------------------------------
+@dataclass
+class Request:
+    rid: int
+    seqs: np.ndarray          # uint8 bases
+    offsets: np.ndarray       # uint64, nreads + 1
+    arrival: float
+    future: concurrent.futures.Future = field(default_factory=concurrent.futures.Future)
+    admitted: float = 0.0
+    finished: float = 0.0
+
+    @property
+    def nbases(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def nreads(self) -> int:
+        return int(self.offsets.size - 1)
+
+
+@dataclass
+class Result:
+    hash: np.ndarray          # uint64
+    pos: np.ndarray           # uint32, relative to the read
+    read_offsets: np.ndarray  # uint64, nreads + 1
+
+
+def window_bound(offsets: np.ndarray, k: int, w: int) -> int:
+    lens = np.diff(np.asarray(offsets, dtype=np.int64))
+    return int(np.maximum(lens - k - w + 2, 0).sum())
+
+
+class Executor:
+    """Runs batches.  ``footprint`` sizes a batch in arena bytes; ``start``
+    enqueues it and returns a handle; ``done`` polls; ``finish`` returns the
+    per-request results (or raises)."""
+
+    def footprint(self, nbases: int, nreads: int, bound: int) -> int:
+        raise NotImplementedError
+
+    def start(self, reqs: List[Request], slot: int):
+        raise NotImplementedError
+
+    def done(self, handle) -> bool:
+        raise NotImplementedError
+
+    def finish(self, handle) -> List[Result]:
+        raise NotImplementedError
+
+    def slots(self) -> int:
+        return 1
+
+    def arena_bytes(self) -> int:
+        raise NotImplementedError
+
+
+def _split(reqs: List[Request], h, p, ro):
+    """Cut batch outputs (read-major) into per-request results."""
+    out = []
+    r0 = 0
+    for q in reqs:
+        n = q.nreads
+        a, e = int(ro[r0]), int(ro[r0 + n])
+        out.append(Result(h[a:e].copy(), p[a:e].copy(), (ro[r0:r0 + n + 1] - ro[r0]).copy()))
+        r0 += n
+    return out
+
+
+def _concat(reqs: List[Request]):
+    nreads = sum(q.nreads for q in reqs)
+    off = np.zeros(nreads + 1, dtype=np.uint64)
+    seqs = np.concatenate([q.seqs for q in reqs]) if reqs else np.zeros(0, np.uint8)
+    r = 0
+    base = 0
+    for q in reqs:
+        n = q.nreads
+        off[r + 1:r + n + 1] = q.offsets[1:] + np.uint64(base)
+        base += q.nbases
+        r += n
+    return seqs, off
+
+
+# ---------------------------------------------------------------------------
+# GPU executor.
+# ---------------------------------------------------------------------------
+class GPUExecutor(Executor):
+    """Batches on the device: one arena allocation holds every in-flight
+    batch's bases, offsets, outputs and workspace; S streams (default
+    priority) run batches concurrently."""
+
+    def __init__(self, k: int, w: int, arena_bytes: Optional[int] = None, streams: int = 4,
+                 canonical: bool = True, hashed: bool = True, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.k, self.w = k, w
+        self.flags = (0 if canonical else _lib.KMER_FORWARD) | (0 if hashed else _lib.HASH_IDENTITY)
+        if arena_bytes is None:
+            free, _ = torch.cuda.mem_get_info()
+            arena_bytes = int(free * 0.5)
+        self.arena_dev = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(streams)]
+        self.free_streams = list(range(streams))
+        self.staging = [None] * streams  # grow-only pinned host buffers, one per stream
+        self.lib = _lib.load()
+
+    def _pinned(self, si: int, nbytes: int):
+        torch = self.torch
+        buf = self.staging[si]
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(nbytes, 1 << 20) * 5 // 4, dtype=torch.uint8, pin_memory=True)
+            self.staging[si] = buf
+        return buf
+
+    def slots(self) -> int:
+        return len(self.streams)
+
+    def arena_bytes(self) -> int:
+        return self.arena_dev.numel()
+
+    def _layout(self, nbases: int, nreads: int, bound: int):
+        R = Arena.round
+        ws = ctypes.c_uint64(0)
+        _lib.check(self.lib.sws_minimizers_batch_workspace(nbases, nreads, self.k, self.w,
+                                                           ctypes.byref(ws)),
+                   "sws_minimizers_batch_workspace")
+        parts = [("seqs", R(nbases)), ("offsets", R(8 * (nreads + 1))), ("hash", R(8 * bound)),
+                 ("pos", R(4 * bound)), ("read", R(4 * bound)), ("read_out", R(8 * (nreads + 1))),
+                 ("ws", R(ws.value))]
+        lay, off = {}, 0
+        for name, n in parts:
+            lay[name] = (off, n)
+            off += n
+        return lay, off
+
+    def footprint(self, nbases, nreads, bound):
+        return self._layout(nbases, nreads, bound)[1]
+
+    def start(self, reqs, slot):
+        torch = self.torch
+        seqs, off = _concat(reqs)
+        nreads, nbases = off.size - 1, int(off[-1])
+        bound = window_bound(off, self.k, self.w)
+        lay, _ = self._layout(nbases, nreads, bound)
+        si = self.free_streams.pop()
+        stream = self.streams[si]
+        base = self.arena_dev.data_ptr() + slot
+
+        def view(name, dtype, count):
+            o, _n = lay[name]
+            t = self.arena_dev[slot + o: slot + o + count * np.dtype(dtype).itemsize]
+            return t
+
+        # stage bases and offsets in this stream's pinned buffer (the previous
+        # batch on this stream has finished, so the buffer is free)
+        pin = self._pinned(si, Arena.round(nbases) + 8 * (nreads + 1))
+        pin_np = pin.numpy()
+        pin_np[:nbases] = seqs
+        ob = Arena.round(nbases)
+        pin_np[ob:ob + 8 * (nreads + 1)] = off.view(np.uint8)
+        with torch.cuda.stream(stream):
+            if nbases:
+                view("seqs", np.uint8, nbases).copy_(pin[:nbases], non_blocking=True)
+            view("offsets", np.int64, nreads + 1).copy_(pin[ob:ob + 8 * (nreads + 1)],
+                                                          non_blocking=True)
+            p = lambda name: ctypes.c_void_p(base + lay[name][0])
+            st = self.lib.sws_minimizers_batch(
+                p("seqs"), p("offsets"), nreads, nbases, self.k, self.w, self.flags, p("hash"),
+                p("pos"), p("read"), bound, p("read_out"), p("ws"), lay["ws"][1],
+                ctypes.c_void_p(stream.cuda_stream))
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        if st != 0:
+            self.free_streams.append(si)
+            _lib.check(st, "sws_minimizers_batch")
+        # keep the pinned staging alive until the copies finished
+        return {"reqs": reqs, "event": ev, "stream": si, "lay": lay, "slot": slot,
+                "nreads": nreads, "bound": bound}
+
+    def done(self, handle) -> bool:
+        return handle["event"].query()
+
+    def finish(self, handle):
+        torch = self.torch
+        handle["event"].synchronize()
+        lay, slot, nreads = handle["lay"], handle["slot"], handle["nreads"]
+        stream = self.streams[handle["stream"]]
+        self.free_streams.append(handle["stream"])
+
+        def dev(name, count, dtype):
+            o, _n = lay[name]
+            nb = count * torch.tensor([], dtype=dtype).element_size()
+            return self.arena_dev[slot + o: slot + o + nb].view(dtype)
+
+        with torch.cuda.stream(stream):
+            ro = dev("read_out", nreads + 1, torch.int64).cpu().numpy().view(np.uint64)
+            total = int(ro[-1])
+            if total == 0xFFFFFFFFFFFFFFFF or total > handle["bound"]:
+                raise _lib.SwsError(_lib.SWS_ERR_DEVICE, "batch kernel reported an internal error")
+            h = dev("hash", total, torch.int64).cpu().numpy().view(np.uint64)
+            p = dev("pos", total, torch.int32).cpu().numpy().view(np.uint32)
+        return _split(handle["reqs"], h, p, ro)
+
+
+# ---------------------------------------------------------------------------
+# CPU fake executor for scheduler tests (oracle-backed).
+# ---------------------------------------------------------------------------
+class FakeExecutor(Executor):
+    """Computes batches on the CPU after `latency(batch)` seconds; requests
+    for which `fail(request)` is true make their batch fail."""
+
+    def __init__(self, k: int, w: int, arena_bytes: int = 1 << 30, slots: int = 2,
+                 latency: Callable[[List[Request]], float] = lambda reqs: 0.001,
+                 fail: Callable[[Request], bool] = lambda q: False, compute=None):
+        self.k, self.w = k, w
+        self._arena = arena_bytes
+        self._slots = slots
+        self.latency = latency
+        self.fail = fail
+        self.compute = compute  # (seqs, offsets, k, w) -> (hash, pos, read, read_offsets)
+        self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=slots)
+        self.inflight = 0
+        self.max_inflight_seen = 0
+        self.batches = []
+
+    def slots(self):
+        return self._slots
+
+    def arena_bytes(self):
+        return self._arena
+
+    def footprint(self, nbases, nreads, bound):
+        return Arena.round(nbases) + Arena.round(16 * (nreads + 1)) + Arena.round(16 * bound) + 256
+
+    def _run(self, reqs):
+        time.sleep(self.latency(reqs))
+        if any(self.fail(q) for q in reqs):
+            raise RuntimeError("injected failure")
+        seqs, off = _concat(reqs)
+        h, p, rd, ro = self.compute(seqs, off, self.k, self.w)
+        return _split(reqs, h, p, ro)
+
+    def start(self, reqs, slot):
+        self.inflight += 1
+        self.max_inflight_seen = max(self.max_inflight_seen, self.inflight)
+        self.batches.append([q.rid for q in reqs])
+        return self.pool.submit(self._run, reqs)
+
+    def done(self, handle):
+        return handle.done()
+
+    def finish(self, handle):
+        self.inflight -= 1
+        return handle.result()
+
+
+# ---------------------------------------------------------------------------
+# Server.
+# ---------------------------------------------------------------------------
+class RequestTooLarge(ValueError):
+    pass
+
+
+class Server:
+    def __init__(self, executor: Executor, k: int, w: int, max_batch_bases: int = 64 << 20,
+                 poll_s: float = 50e-6):
+        self.ex = executor
+        self.k, self.w = k, w
+        self.arena = Arena(executor.arena_bytes())
+        self.max_batch_bases = max_batch_bases
+        self.poll_s = poll_s
+        self.queue = collections.deque()
+        self.lock = threading.Lock()
+        self.wake = threading.Event()
+        self.inflight = []  # (handle, slot, nbytes, reqs)
+        self.stop_flag = False
+        self.thread = None
+        self.next_id = 0
+        self.completed: List[Request] = []
+
+    # -- client side --------------------------------------------------------
+    def submit(self, seqs: np.ndarray, offsets: np.ndarray, arrival: Optional[float] = None):
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        q = Request(self.next_id, np.ascontiguousarray(seqs, dtype=np.uint8), off,
+                    time.perf_counter() if arrival is None else arrival)
+        self.next_id += 1
+        need = self.ex.footprint(q.nbases, q.nreads, window_bound(off, self.k, self.w))
+        if need > self.arena.size:
+            q.future.set_exception(RequestTooLarge(
+                "request needs %d arena bytes, the arena has %d" % (need, self.arena.size)))
+            return q.future
+        with self.lock:
+            self.queue.append(q)
+        self.wake.set()
+        return q.future
+
+    def start(self):
+        self.thread = threading.Thread(target=self._loop, name="sws-scheduler", daemon=True)
+        self.thread.start()
+        return self
+
+    def stop(self, drain: bool = True, timeout: float = 60.0):
+        if drain:
+            t0 = time.perf_counter()
+            while (self.queue or self.inflight) and time.perf_counter() - t0 < timeout:
+                time.sleep(0.001)
+        self.stop_flag = True
+        self.wake.set()
+        if self.thread:
+            self.thread.join(timeout)
+
+    # -- scheduler ----------------------------------------------------------
+    def _form_batch(self):
+        """Oldest-first requests that fit together in free arena bytes."""
+        reqs, nb, nr, bound = [], 0, 0, 0
+        with self.lock:
+            while self.queue:
+                q = self.queue[0]
+                b2 = bound + window_bound(q.offsets, self.k, self.w)
+                need = self.ex.footprint(nb + q.nbases, nr + q.nreads, b2)
+                if reqs and nb + q.nbases > self.max_batch_bases:
+                    break
+                if need > self.arena.free_bytes:
+                    break
+                reqs.append(self.queue.popleft())
+                nb, nr, bound = nb + q.nbases, nr + q.nreads, b2
+        if not reqs:
+            return None
+        need = self.ex.footprint(nb, nr, bound)
+        slot = self.arena.alloc(need)
+        if slot is None:  # fragmented: put them back, retry after a completion
+            with self.lock:
+                self.queue.extendleft(reversed(reqs))
+            return None
+        return reqs, slot, need
+
+    def _loop(self):
+        while not self.stop_flag:
+            progressed = False
+            # completions
+            for item in list(self.inflight):
+                handle, slot, nbytes, reqs = item
+                if self.ex.done(handle):
+                    self.inflight.remove(item)
+                    try:
+                        results = self.ex.finish(handle)
+                        now = time.perf_counter()
+                        for q, r in zip(reqs, results):
+                            q.finished = now
+                            q.future.set_result(r)
+                    except Exception as exc:  # the batch failed: isolate per request
+                        self._retry_alone(reqs, exc)
+                    self.arena.release(slot, nbytes)
+                    self.completed.extend(reqs)
+                    progressed = True
+            # admissions
+            while len(self.inflight) < self.ex.slots() and self.queue:
+                b = self._form_batch()
+                if b is None:
+                    break
+                reqs, slot, need = b
+                now = time.perf_counter()
+                for q in reqs:
+                    q.admitted = now
+                try:
+                    handle = self.ex.start(reqs, slot)
+                except Exception as exc:
+                    self.arena.release(slot, need)
+                    for q in reqs:
+                        q.future.set_exception(exc)
+                    continue
+                self.inflight.append((handle, slot, need, reqs))
+                progressed = True
+            if not progressed:
+                if not self.inflight and not self.queue:
+                    self.wake.wait(0.01)
+                    self.wake.clear()
+                else:
+                    time.sleep(self.poll_s)
+
+    def _retry_alone(self, reqs, exc):
+        """A failed batch is re-run one request at a time, so one bad request
+        fails alone."""
+        if len(reqs) == 1:
+            reqs[0].future.set_exception(exc)
+            return
+        for q in reqs:
+            need = self.ex.footprint(q.nbases, q.nreads, window_bound(q.offsets, self.k, self.w))
+            slot = self.arena.alloc(need)
+            if slot is None:
+                q.future.set_exception(exc)
+                continue
+            try:
+                h = self.ex.start([q], slot)
+                while not self.ex.done(h):
+                    time.sleep(self.poll_s)
+                r = self.ex.finish(h)[0]
+                q.finished = time.perf_counter()
+                q.future.set_result(r)
+            except Exception as e2:
+                q.future.set_exception(e2)
+            finally:
+                self.arena.release(slot, need)
+
+
+def latency_stats(reqs: List[Request]):
+    lat = np.array([q.finished - q.arrival for q in reqs if q.finished > 0])
+    if lat.size == 0:
+        return {}
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "n": int(lat.size)}
