@@ -37,6 +37,26 @@ ALU_OPS_PER_BASE = 62
 METRIC = "Gbases/s minimizers (k=15,w=10) + % HBM peak; batched vs per-read launch; p99 ms"
 
 
+def profiled_traffic(profile_name):
+    """HBM bytes per launch recorded in a committed rocprofv3 summary under
+    profiles/, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile_name)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k_, v_ = line.strip().split(":", 1)
+            fields[k_.strip()] = v_.strip()
+    src = os.path.join(ROOT, fields.get("source", ""))
+    if not os.path.isfile(src) or "traffic_bytes_per_launch" not in fields:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -120,7 +140,154 @@ def bench_sliding(torch, steps, warmup, quick):
                                                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}
                 del y
     out["n2^28_sweep"] = sweep
+    # the plain kernel's roofline: + mod 2^32, w = 16, n = 2^28 (HBM-bound)
+    ref = sweep.get("add_generic_w16")
+    if ref:
+        out["roofline_add_w16"] = {"bound": "hbm", "achieved": ref["GB/s"], "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(ref["GB/s"] / HBM_PEAK_GBS, 3),
+                                   "traffic": profiled_traffic(
+                                       "sliding_generic_kernel_add_w16_n2p28.txt")}
     return out
+
+
+def bench_batch(torch, quick):
+    """Uneven reads in one launch (bucketed, tuned, graph) against one launch
+    per read."""
+    import ctypes
+    import numpy as np
+    import paper_1811_10074_amd as sws
+    from paper_1811_10074_amd import _lib, batch, inputs, tune
+
+    scale = 10 if quick else 1
+    k, w = 15, 10
+    log("generating the uneven-read batch")
+    seqs, off = inputs.read_batch(n_short=2_000_000 // scale, n_long=100_000 // scale, seed=3)
+    nreads, total = off.size - 1, int(off[-1])
+    out = {"workload": "%d reads of 150 b + %d lognormal long reads (median 8 kb, sigma 0.8, "
+                       "1-100 kb), 1%% N, k=15, w=10" % (2_000_000 // scale, 100_000 // scale),
+           "reads": int(nreads), "bases": total}
+    # one launch over all reads, default block size
+    runner = batch.BatchRunner(torch.from_numpy(seqs).cuda(), off, k, w)
+    ms, med, _ = time_launches(torch, runner.launch, 5, 2)
+    out["one_launch"] = {"ms": round(ms, 3), "Gbases/s": round(total / (ms / 1e3) / 1e9, 2),
+                         "minimizers": int(runner.read_out[-1].item())}
+    del runner
+    torch.cuda.empty_cache()
+    # tuned block size per length bucket, every bucket in one HIP graph
+    sub = slice(0, max(off.size // 20, 2))
+    soff = off[sub] - off[0]
+    table, timings = tune.tune(seqs[: int(soff[-1])], soff, k, w, reps=3)
+    bb = batch.BucketedBatch(seqs, off, k, w, tune_table=table)
+    bb.capture()
+    ms_g, med_g, _ = time_launches(torch, bb.replay, 5, 2)
+    out["bucketed_graph"] = {"ms": round(ms_g, 3), "Gbases/s": round(total / (ms_g / 1e3) / 1e9, 2),
+                             "tune_table": {str(b): t for b, t in table.items()},
+                             "tune_ms": {kk: round(v, 3) for kk, v in timings.items()}}
+    del bb
+    torch.cuda.empty_cache()
+    # baseline: one library call per read (no batching), on the first reads
+    nsample = 2000 if quick else 20000
+    dev = torch.from_numpy(seqs[: int(off[nsample])]).cuda()
+    maxlen = int(np.diff(off[: nsample + 1].astype(np.int64)).max())
+    r = sws.MinimizerRunner(maxlen, k, w)
+    lib = _lib.load()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    base_ptr = dev.data_ptr()
+    args = [(ctypes.c_void_p(base_ptr + int(off[i])), int(off[i + 1] - off[i])) for i in range(nsample)]
+    hp, pp, cp, wp = (ctypes.c_void_p(t.data_ptr()) for t in (r.hash, r.pos, r.count, r.workspace))
+    wsz = r.workspace.numel()
+
+    def per_read():
+        for ptr, n in args:
+            lib.sws_minimizers(ptr, n, k, w, 0, hp, pp, r.capacity, cp, wp, wsz, stream)
+
+    ms_p, _, _ = time_launches(torch, per_read, 1, 1)
+    sbases = int(off[nsample])
+    per_read_rate = sbases / (ms_p / 1e3) / 1e9
+    out["per_read_launch"] = {"sample_reads": nsample, "sample_bases": sbases, "ms": round(ms_p, 3),
+                              "us_per_read": round(ms_p * 1e3 / nsample, 2),
+                              "Gbases/s": round(per_read_rate, 4)}
+    best = max(out["one_launch"]["Gbases/s"], out["bucketed_graph"]["Gbases/s"])
+    out["speedup_vs_per_read"] = round(best / per_read_rate, 1)
+    return out
+
+
+def bench_serve(torch, quick):
+    """Poisson requests (k=19, w=19) through the continuous-batching server,
+    open loop at the arrival times and closed loop, against one unbatched
+    launch per request."""
+    import numpy as np
+    from paper_1811_10074_amd import inputs
+    from paper_1811_10074_amd.serve import GPUExecutor, Server, latency_stats
+
+    k, w = 19, 19
+    dur = 3.0 if quick else 10.0
+    log("generating %.0f s of Poisson requests" % dur)
+    reqs = inputs.poisson_requests(rate=200.0, duration_s=dur, seed=4)
+    bases = sum(int(o[-1]) for _, _, o in reqs)
+    out = {"workload": "Poisson arrivals at 200 req/s for %.0f s, 1-4096 reads per request "
+                       "(log-uniform), read lengths from the uneven-read mix, 1%% N, k=19, w=19"
+                       % dur, "requests": len(reqs), "bases": bases}
+
+    def run(max_batch, streams, open_loop):
+        ex = GPUExecutor(k, w, arena_bytes=16 << 30, streams=streams)
+        srv = Server(ex, k, w, max_batch_bases=max_batch).start()
+        # warm up kernels and pinned buffers
+        srv.submit(reqs[0][1], reqs[0][2]).result(timeout=60)
+        srv.completed.clear()
+        t0 = time.perf_counter()
+        futs = []
+        for t, sq, of in reqs:
+            if open_loop:
+                d = t0 + t - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+            futs.append(srv.submit(sq, of))
+        for f in futs:
+            f.result(timeout=600)
+        wall = time.perf_counter() - t0
+        srv.stop()
+        st = latency_stats(srv.completed)
+        st["Gbases/s"] = round(bases / wall / 1e9, 3)
+        st["wall_s"] = round(wall, 3)
+        del ex, srv
+        torch.cuda.empty_cache()
+        return {kk: (round(v, 3) if isinstance(v, float) else v) for kk, v in st.items()}
+
+    out["batched_open_loop"] = run(64 << 20, 4, True)
+    out["batched_closed_loop"] = run(64 << 20, 4, False)
+    out["unbatched_closed_loop"] = run(1, 1, False)
+    out["unbatched_open_loop"] = run(1, 1, True)
+    return out
+
+
+def profile_run(torch, args):
+    """A plain device copy of exactly 1 GiB (its FETCH_SIZE / WRITE_SIZE
+    calibrate the counters), then the kernel under study."""
+    import numpy as np
+    import paper_1811_10074_amd as sws
+    from paper_1811_10074_amd import inputs
+
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    if args.profile == "minimizer":
+        n = 1 << 26
+        seq = torch.from_numpy(inputs.dna(n, seed=1)).cuda()
+        r = sws.MinimizerRunner(n, 15, 10)
+        ms, med, _ = time_launches(torch, lambda: r.launch(seq=seq), args.steps, args.warmup)
+        print(json.dumps({"kernel": "minimizer", "ms_per_step": ms, "count": int(r.count.item())}))
+    else:
+        n = 1 << 28
+        x = torch.from_numpy(inputs.uniform_u32(n, seed=2).view(np.int32)).cuda()
+        y = torch.empty(n - 15, dtype=torch.int32, device="cuda")
+        ms, med, _ = time_launches(torch, lambda: sws.sliding_sum("add", 16, x, out=y), args.steps,
+                                   args.warmup)
+        print(json.dumps({"kernel": "sliding add w=16 n=2^28", "ms_per_step": ms}))
 
 
 def main():
@@ -132,6 +299,9 @@ def main():
     ap.add_argument("--primary-only", action="store_true",
                     help="only the timed minimizer steps (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", choices=["minimizer", "sliding"],
+                    help="run only a 1-GiB plain copy (counter calibration) and the named kernel "
+                         "--steps times, for rocprofv3")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -146,6 +316,8 @@ def main():
     from paper_1811_10074_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.profile:
+        return profile_run(torch, args)
     k, w, n = 15, 10, 1 << 26
     log("generating %d bases (seed 1)" % n)
     seq_np = inputs.dna(n, seed=1)
@@ -190,7 +362,7 @@ def main():
             "peak": round(ALU_PEAK_TOPS, 2),
             "unit": "Tops/s",
             "frac": round(ALU_OPS_PER_BASE * n / (ms / 1e3) / 1e12 / ALU_PEAK_TOPS, 3),
-            "traffic": None,
+            "traffic": profiled_traffic("minimizer_wave_kernel_64Mbases_k15_w10.txt"),
         },
         "hbm": {"algorithmic_bytes": algo_bytes,
                 "GB/s": round(algo_bytes / (ms / 1e3) / 1e9, 1),
@@ -215,6 +387,12 @@ def main():
     torch.cuda.empty_cache()
     log("sliding-sum extras")
     line["sliding"] = bench_sliding(torch, args.steps, args.warmup, args.quick)
+    torch.cuda.empty_cache()
+    log("batched reads")
+    line["batched"] = bench_batch(torch, args.quick)
+    torch.cuda.empty_cache()
+    log("serving")
+    line["serving"] = bench_serve(torch, args.quick)
     print(json.dumps(line))
 
 
