@@ -49,10 +49,16 @@ def profiled_traffic(profile_name):
         if ":" in line:
             k_, v_ = line.strip().split(":", 1)
             fields[k_.strip()] = v_.strip()
-    src = os.path.join(ROOT, fields.get("source", ""))
-    if not os.path.isfile(src) or "traffic_bytes_per_launch" not in fields:
+    # source: the kernel's file and the headers it includes, comma-separated;
+    # source_sha256 covers their bytes concatenated in that order
+    srcs = [os.path.join(ROOT, f.strip()) for f in fields.get("source", "").split(",") if f.strip()]
+    if not srcs or not all(os.path.isfile(f) for f in srcs) \
+            or "traffic_bytes_per_launch" not in fields:
         return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+    h = hashlib.sha256()
+    for f in srcs:
+        h.update(open(f, "rb").read())
+    if h.hexdigest() != fields.get("source_sha256"):
         return None
     return float(fields["traffic_bytes_per_launch"])
 

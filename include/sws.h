@@ -225,10 +225,20 @@ int sws_minimizers_batch(const uint8_t *seqs, const uint64_t *d_offsets, uint32_
 /*
  * Sets the threads per workgroup used by the minimizer kernels for batches
  * whose mean read length falls in bucket `bucket` (0: < 1 kb, 1: < 16 kb,
- * 2: longer).  threads must be 128, 256 or 512.  Applies to later calls in
- * this process.  Errors: SWS_ERR_INVALID.
+ * 2: longer).  threads must be 64, 128, 256 or 512.  Applies to later calls
+ * in this process.  Errors: SWS_ERR_INVALID.
  */
 int sws_set_minimizer_block(uint32_t bucket, uint32_t threads);
+
+/*
+ * Sets how many wavefronts a generic-path sliding-sum launch aims for.  The
+ * input is cut into slabs of 64*R elements (R = 8, 16 or 32 by window and
+ * operator) and each wavefront streams ceil(slabs / waves) consecutive slabs,
+ * so fewer waves means longer streams per wave.  0 restores the default
+ * (32768: 128 per compute unit).  Results do not depend on it.  Applies to
+ * later calls in this process.  Errors: SWS_ERR_INVALID (waves > 2^24).
+ */
+int sws_set_sliding_waves(uint64_t waves);
 
 /* Human-readable name of a status code (static storage). */
 const char *sws_status_str(int status);

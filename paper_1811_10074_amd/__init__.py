@@ -83,6 +83,12 @@ def sliding_sum(op: str, w: int, x, path: str = "auto", out=None):
     return out
 
 
+def set_sliding_waves(waves: int = 0) -> None:
+    """Wavefronts a generic-path sliding_sum launch aims for (0: default);
+    each streams ceil(slabs / waves) consecutive slabs.  Process-wide."""
+    check(_lib.load().sws_set_sliding_waves(int(waves)), "sws_set_sliding_waves")
+
+
 def pack2bit(seq, with_invalid: bool = True):
     """ASCII uint8 tensor -> (packed int32[ceil(n/16)], invalid int32[ceil(n/32)] or None)."""
     torch = _torch()

@@ -46,6 +46,7 @@ _SIGNATURES = {
     "sws_minimizers_batch": (c_int, [c_vp, c_vp, c_u32, c_u64, c_u32, c_u32, c_u32, c_vp, c_vp,
                                      c_vp, c_u64, c_vp, c_vp, c_u64, c_vp]),
     "sws_set_minimizer_block": (c_int, [c_u32, c_u32]),
+    "sws_set_sliding_waves": (c_int, [c_u64]),
 }
 
 

@@ -16,6 +16,9 @@ bool known_flags(uint32_t flags) {
 
 // Threads per workgroup of the minimizer kernels, per read-length bucket.
 uint32_t g_min_block[3] = {256, 256, 256};
+// Wavefronts a generic sliding-sum launch aims for (0: the default).
+constexpr uint64_t kDefaultSlidingWaves = 256ull * 128ull;
+uint64_t g_sliding_waves = 0;
 
 uint32_t bucket_of(uint64_t total_bases, uint64_t nreads) {
     const uint64_t mean = nreads ? total_bases / nreads : total_bases;
@@ -116,8 +119,11 @@ int sws_sliding_sum_ex(int op, uint64_t w, const void* x, uint64_t n, void* y, i
                                                                                : SWS_ERR_DEVICE;
     }
     if (w > sws::generic_max_window()) return SWS_ERR_UNSUPPORTED;
-    return sws::launch_sliding_generic(op, x, n, (uint32_t)w, y, count, s) == 0 ? SWS_OK
-                                                                               : SWS_ERR_DEVICE;
+    return sws::launch_sliding_generic(op, x, n, (uint32_t)w, y, count,
+                                       g_sliding_waves ? g_sliding_waves : kDefaultSlidingWaves,
+                                       s) == 0
+               ? SWS_OK
+               : SWS_ERR_DEVICE;
 }
 
 int sws_sliding_sum(int op, uint64_t w, const void* x, uint64_t n, void* y, hipStream_t s) {
@@ -252,6 +258,12 @@ int sws_minimizers_batch(const uint8_t* seqs, const uint64_t* d_offsets, uint32_
     const uint32_t nt = g_min_block[bucket_of(total_bases, nreads)];
     return sws::launch_minimizers_batch(in, a, nt > 256 ? 256 : nt, workspace, s) == 0
                ? SWS_OK : SWS_ERR_DEVICE;
+}
+
+int sws_set_sliding_waves(uint64_t waves) {
+    if (waves > (1ull << 24)) return SWS_ERR_INVALID;
+    g_sliding_waves = waves;
+    return SWS_OK;
 }
 
 int sws_set_minimizer_block(uint32_t bucket, uint32_t threads) {

@@ -470,10 +470,9 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
     //    aligned to multiples of w inside the tile
     const uint32_t span = (w + kR - 1) / kR;
     const uint32_t m0 = ((uint32_t)tid * kR) % w;
-    uint64_t heads, ends;
-    lane_masks<kR>(m0, w, head_pattern(w, kR), heads, ends);
+    const HeadMask<kR> heads = lane_heads<kR>(m0, w, head_pattern<kR>(w));
     slab_prefix<Op, kR>(pf, heads, span, lane, Op::identity());
-    slab_suffix<Op, kR>(sf, ends, span, lane);
+    slab_suffix<Op, kR>(sf, heads, span, lane);
     if (lane == kWave - 1) s_carryF[wv] = pf[kR - 1];
     if (lane == 0) s_carryB[wv] = sf[0];
 #pragma unroll

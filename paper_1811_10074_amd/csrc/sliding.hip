@@ -24,6 +24,15 @@
 // LDS ring, from which each lane reads Pf_{i+w-1}.  No workgroup barrier, no
 // global scratch; HBM sees each element read once and each output written once.
 //
+// Ring layout: rows of R elements (one lane's run), each padded by one
+// element, so lane l's writes of element e and its reads of Pf_{i+w-1} are
+// both one row apart across lanes and free of bank conflicts.  Rows 0..63 and
+// 64..127 are the two slab regions; rows from 128 on repeat the first rows of
+// region 0, so that the reads of a slab in region 1 never wrap.  A read
+// address is then the lane's row base plus a wave-uniform offset.  The region
+// that is dead at each moment doubles as the staging area through which
+// coalesced 16-byte loads and stores are redistributed into lane runs.
+//
 // Log path (MIN and MAX only; Sec. 3.1, the commutative case).  With
 // m^(1) = x, m^(2s)_i = m^(s)_i (+) m^(s)_{i+s} and 2^t the largest power of two
 // not above w, y_i = m^(2^t)_i (+) m^(2^t)_{i+w-2^t}; the two halves overlap,
@@ -34,35 +43,39 @@
 #include "sws_internal.hpp"
 #include "sws_scan.hpp"
 
+#include <type_traits>
+
 namespace sws {
 
 // ---------------------------------------------------------------------------
 // Generic path.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t ring_index(uint32_t r) { return r + (r >> 4); }
-
 // Coalesced movement of one slab between HBM and a lane's run of R elements:
 // lane l loads/stores the 16-byte chunks l, l + 64, l + 128, ... of the slab
 // (every instruction covers 1 KB of contiguous memory) and the chunks change
-// hands through a per-wave LDS staging area padded by 16 bytes per run.
+// hands through a per-wave LDS staging area holding one 16-byte pad per four
+// lane runs (64 * kChunks + 16 chunks: one ring region).
 template <class T, int R>
 struct SlabIO {
     static constexpr int kChunks = (int)(R * sizeof(T) / 16);  // chunks per lane run
-    static constexpr int kStageWords = kWave * (kChunks + 1) * 4;
+    static constexpr int kStageWords = (kWave * kChunks + 16) * 4;
 
     static __device__ __forceinline__ uint32_t stage_off(int chunk) {  // in u32 words
-        return (uint32_t)((chunk / kChunks) * (kChunks + 1) + chunk % kChunks) * 4u;
+        return (uint32_t)(chunk + chunk / (4 * kChunks)) * 4u;
     }
 
-    // raw[i] = chunk (i * 64 + lane) of the slab starting at element p0;
-    // elements at or past n read as the identity.
+    // raw[i] = chunk (i * 64 + lane) of the slab starting at element p0.
+    // CHECK = false: the caller guarantees an aligned slab wholly below n, and
+    // the loads are straight-line code.  CHECK = true: elements at or past n
+    // read as the identity.
+    template <bool CHECK>
     static __device__ __forceinline__ void load(const T* __restrict__ x, uint64_t n, uint64_t p0,
                                                 int lane, bool vec, T ident, u32x4 (&raw)[kChunks]) {
         const uint64_t per = 16 / sizeof(T);
 #pragma unroll
         for (int i = 0; i < kChunks; ++i) {
             const uint64_t e0 = p0 + (uint64_t)(i * kWave + lane) * per;
-            if (vec && e0 + per <= n) {
+            if (!CHECK || (vec && e0 + per <= n)) {
                 raw[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(x + e0));
             } else {
                 const uint32_t* xw = reinterpret_cast<const uint32_t*>(x);
@@ -96,11 +109,14 @@ struct SlabIO {
         wave_lds_sync();
     }
 
-    // this lane's run -> coalesced stores of the slab at element p0 (below limit)
+    // this lane's run -> coalesced stores of the slab at element p0; with
+    // CHECK = false the slab is aligned and wholly below limit.
+    template <bool CHECK>
     static __device__ __forceinline__ void store(T* __restrict__ y, uint64_t limit, uint64_t p0,
                                                  int lane, bool vec, uint32_t* stage,
                                                  const T (&v)[R]) {
         const u32x4* q = reinterpret_cast<const u32x4*>(v);
+        wave_lds_sync();  // earlier reads of the staging area have completed
 #pragma unroll
         for (int i = 0; i < kChunks; ++i)
             *reinterpret_cast<u32x4*>(stage + stage_off(lane * kChunks + i)) = q[i];
@@ -110,7 +126,7 @@ struct SlabIO {
         for (int i = 0; i < kChunks; ++i) {
             const u32x4 c = *reinterpret_cast<const u32x4*>(stage + stage_off(i * kWave + lane));
             const uint64_t e0 = p0 + (uint64_t)(i * kWave + lane) * per;
-            if (vec && e0 + per <= limit) {
+            if (!CHECK || (vec && e0 + per <= limit)) {
                 __builtin_nontemporal_store(c, reinterpret_cast<u32x4*>(y + e0));
             } else {
                 uint32_t* yw = reinterpret_cast<uint32_t*>(y);
@@ -126,80 +142,117 @@ struct SlabIO {
     }
 };
 
+// Suffix sums at segment heads are never read (a window starting at a head is
+// one whole segment, Pf alone); storing the identity there lets every output
+// take the form Sf (+) Pf.
+template <int R, class T>
+__device__ __forceinline__ void heads_to_identity(T (&sf)[R], HeadMask<R> h, T ident) {
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+        if (head_bit<R>(h, e)) sf[e] = ident;
+}
+
+// Ring rows a window of w needs: two regions of 64 rows plus the repeated
+// rows read past row 127, rounded up to a multiple of 4 (keeps every region
+// 16-byte aligned).
+template <int R>
+__host__ __device__ constexpr uint32_t ring_rows(uint32_t w) {
+    return (128u + (R + w - 2u) / R + 3u) & ~3u;
+}
+
 template <class Op, int R, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
     const typename Op::T* __restrict__ x, uint64_t n, uint32_t w, typename Op::T* __restrict__ y,
-    uint64_t count, uint64_t total_slabs, uint64_t slabs_per_wave, int vec) {
+    uint64_t count, uint64_t total_slabs, uint64_t slabs_per_wave, int vec, uint32_t rows) {
     using T = typename Op::T;
     using IO = SlabIO<T, R>;
     constexpr uint32_t S = kWave * R;
-    constexpr uint32_t RING = 2 * S;
-    __shared__ T ring_all[WAVES][RING + RING / 16];
-    __shared__ uint32_t stage_all[WAVES][IO::kStageWords];
+    constexpr uint32_t RS = R + 1;              // ring row stride (elements)
+    constexpr uint32_t REGION = kWave * RS;     // elements per slab region
+    static_assert(IO::kStageWords * 4 <= REGION * sizeof(T), "staging fits a region");
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = lane_id();
-    const int wv = (int)(threadIdx.x >> 6);
-    T* ring = ring_all[wv];
-    uint32_t* stage = stage_all[wv];
+    const int wv = wave_id();
+    T* ring = reinterpret_cast<T*>(lds_raw) + (size_t)wv * rows * RS;
+    auto stage_of = [&](uint32_t region) {
+        return reinterpret_cast<uint32_t*>(ring + region * REGION);
+    };
     const uint64_t gw = (uint64_t)blockIdx.x * WAVES + (uint64_t)wv;
     const uint64_t s0 = gw * slabs_per_wave;
     if (s0 >= total_slabs) return;
     const uint64_t s1 = s0 + slabs_per_wave < total_slabs ? s0 + slabs_per_wave : total_slabs;
 
     const uint32_t span = (w + R - 1) / R;
-    const uint32_t lane_mod = (uint32_t)((uint32_t)(lane * R) % w);
+    const uint32_t mirror = (R + w - 2u) / R;  // rows of region 0 repeated from row 128
+    const uint32_t lane_row = (uint32_t)lane * RS;
+    const uint32_t lane_mod = (uint32_t)(((uint64_t)lane * R) % w);
     const uint32_t slab_mod_step = S % w;
-    const uint64_t pat = head_pattern(w, R);
+    const HeadMask<R> pat = head_pattern<R>(w);
     const T ident = Op::identity();
     const bool v16 = vec != 0;
 
     // slab A = s0: prefix sums into ring half 0, suffix sums in registers
     uint32_t mA = (uint32_t)((s0 * (uint64_t)S) % w);
-    uint64_t headsA, endsA;
+    HeadMask<R> headsA;
     T sfA[R];
     T carryA;
     u32x4 raw[IO::kChunks];
-    IO::load(x, n, s0 * S, lane, v16, ident, raw);
+    IO::template load<true>(x, n, s0 * S, lane, v16, ident, raw);
     {
         T v[R];
-        IO::to_run(stage, lane, raw, v);
+        IO::to_run(stage_of(1), lane, raw, v);
         uint32_t m0 = mA + lane_mod;
         m0 = m0 >= w ? m0 - w : m0;
-        lane_masks<R>(m0, w, pat, headsA, endsA);
+        headsA = lane_heads<R>(m0, w, pat);
 #pragma unroll
         for (int e = 0; e < R; ++e) sfA[e] = v[e];
         slab_prefix<Op, R>(v, headsA, span, lane, ident);
 #pragma unroll
-        for (int e = 0; e < R; ++e) ring[ring_index((uint32_t)lane * R + e)] = v[e];
+        for (int e = 0; e < R; ++e) ring[lane_row + e] = v[e];
         carryA = lane_value(v[R - 1], kWave - 1);
-        slab_suffix<Op, R>(sfA, endsA, span, lane);
+        slab_suffix<Op, R>(sfA, headsA, span, lane);
+        heads_to_identity<R>(sfA, headsA, ident);
     }
-    IO::load(x, n, (s0 + 1) * S, lane, v16, ident, raw);  // slab B
+    IO::template load<true>(x, n, (s0 + 1) * S, lane, v16, ident, raw);  // slab B
     uint32_t half = 0;  // ring half holding slab A's prefix sums
 
-    for (uint64_t s = s0; s < s1; ++s) {
+    // One step: slab A = s gets its outputs, slab B = s + 1 (in raw) becomes A.
+    // MODE 0: every access in range and slab s + 2 is loaded into raw;
+    // MODE 1: every access in range, nothing left to load (the last slab of
+    // the wave); MODE 2: accesses checked against n and count.
+    auto step = [&](uint64_t s, auto mode) {
+        constexpr int MODE = decltype(mode)::value;
+        constexpr bool CHECK = MODE == 2;
         const uint64_t baseA = s * S;
         uint32_t mB = mA + slab_mod_step;
         mB = mB >= w ? mB - w : mB;
         T sfB[R];
-        uint64_t headsB, endsB;
+        HeadMask<R> headsB;
         {
             T v[R];
-            IO::to_run(stage, lane, raw, v);
+            IO::to_run(stage_of(half ^ 1u), lane, raw, v);  // B's region is free
             // prefetch slab s + 2 while B and A are computed
-            if (s + 1 < s1) IO::load(x, n, baseA + 2 * (uint64_t)S, lane, v16, ident, raw);
+            if (MODE == 0 || (MODE == 2 && s + 1 < s1))
+                IO::template load<CHECK>(x, n, baseA + 2 * (uint64_t)S, lane, v16, ident, raw);
             uint32_t m0 = mB + lane_mod;
             m0 = m0 >= w ? m0 - w : m0;
-            lane_masks<R>(m0, w, pat, headsB, endsB);
+            headsB = lane_heads<R>(m0, w, pat);
 #pragma unroll
             for (int e = 0; e < R; ++e) sfB[e] = v[e];
             slab_prefix<Op, R>(v, headsB, span, lane, carryA);
-            const uint32_t off = (half ^ 1u) * S;
+            T* rowB = ring + (half ^ 1u) * REGION + lane_row;
 #pragma unroll
-            for (int e = 0; e < R; ++e) ring[ring_index(off + (uint32_t)lane * R + e)] = v[e];
+            for (int e = 0; e < R; ++e) rowB[e] = v[e];
+            if (half == 1u && (uint32_t)lane < mirror) {  // B in region 0: repeat its first rows
+#pragma unroll
+                for (int e = 0; e < R; ++e) rowB[2 * REGION + e] = v[e];
+            }
             carryA = lane_value(v[R - 1], kWave - 1);
-            slab_suffix<Op, R>(sfB, endsB, span, lane);
+            slab_suffix<Op, R>(sfB, headsB, span, lane);
+            heads_to_identity<R>(sfB, headsB, ident);
         }
         // the last segment of A continues into B: append B's leading suffix
+        // (B's first element is not a head here, so sfB[0] in lane 0 is real)
         {
             const T c = lane_value(sfB[0], 0);
             const uint32_t last = (mA + S - 1u) % w;
@@ -207,27 +260,54 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
                 const uint32_t head_rel = S - 1u - last;
 #pragma unroll
                 for (int e = 0; e < R; ++e)
-                    if ((uint32_t)lane * R + e >= head_rel) sfA[e] = Op::combine(sfA[e], c);
+                    if ((uint32_t)lane * R + e > head_rel) sfA[e] = Op::combine(sfA[e], c);
             }
         }
         wave_lds_sync();
-        // outputs of slab A: y_i = Pf_{i+w-1} at a head, Sf_i (+) Pf_{i+w-1} elsewhere
+        // outputs of slab A: y_i = Pf_{i+w-1} at a head, Sf_i (+) Pf_{i+w-1}
+        // elsewhere; sfA holds the identity at heads, so one form serves both
         {
             T out[R];
-            const uint32_t aoff = half * S;
+            // Pf_{i+w-1} for element e of this lane: row base + (c + e) + (c + e) / R
+            // past the start of A's region, c = w - 1 (uniform)
+            const T* rowA = ring + half * REGION + lane_row;
 #pragma unroll
             for (int e = 0; e < R; ++e) {
-                const uint32_t r = (aoff + (uint32_t)lane * R + e + w - 1u) & (RING - 1u);
-                const T pf = ring[ring_index(r)];
-                out[e] = ((headsA >> e) & 1ull) ? pf : Op::combine(sfA[e], pf);
+                const uint32_t q = w - 1u + (uint32_t)e;
+                out[e] = Op::combine(sfA[e], rowA[q + q / R]);
             }
-            IO::store(y, count, baseA, lane, v16, stage, out);
+            IO::template store<CHECK>(y, count, baseA, lane, v16, stage_of(half), out);
         }
 #pragma unroll
         for (int e = 0; e < R; ++e) sfA[e] = sfB[e];
         headsA = headsB;
         mA = mB;
         half ^= 1u;
+    };
+    // Steps whose prefetch (slab s + 2) lies below n and whose outputs (slab
+    // s) lie below count, on aligned buffers, run without bounds checks; the
+    // last step of a wave loads nothing, and the last waves check every
+    // access.  The first unchecked step is peeled so that both ways into the
+    // loop leave the same memory operations in flight (the prefetch, then the
+    // stores); the wait for the prefetched slab then need not wait for the
+    // stores.
+    using M0 = std::integral_constant<int, 0>;
+    using M1 = std::integral_constant<int, 1>;
+    using M2 = std::integral_constant<int, 2>;
+    const uint64_t by_count = count / S;  // s + 1 <= count / S: outputs in range
+    uint64_t s = s0;
+    if (v16) {
+        const uint64_t by_n = n / S >= 3 ? n / S - 2 : 0;  // s + 3 <= n / S
+        uint64_t pf_end = by_n < by_count ? by_n : by_count;
+        if (pf_end > s1 - 1) pf_end = s1 - 1;
+        if (s < pf_end) {
+            step(s++, M0());
+            for (; s < pf_end; ++s) step(s, M0());
+        }
+    }
+    for (; s < s1; ++s) {
+        if (v16 && s < by_count && s + 1 == s1) step(s, M1());
+        else step(s, M2());
     }
 }
 
@@ -273,20 +353,20 @@ __global__ __launch_bounds__(NT) void sliding_log_kernel(const uint32_t* __restr
 // ---------------------------------------------------------------------------
 template <class Op, int R, int WAVES>
 static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
-                          hipStream_t s) {
+                          uint64_t target_waves, hipStream_t s) {
     using T = typename Op::T;
     constexpr uint64_t S = kWave * R;
     const uint64_t total_slabs = (count + S - 1) / S;
-    // aim for about 8 waves per SIMD-slot-round: 256 CUs x 32 waves
-    const uint64_t target_waves = 256ull * 32ull;
     uint64_t spw = (total_slabs + target_waves - 1) / target_waves;
     if (spw < 1) spw = 1;
     const uint64_t waves = (total_slabs + spw - 1) / spw;
     const uint64_t blocks = (waves + WAVES - 1) / WAVES;
     const int vec = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0 ? 1 : 0;
+    const uint32_t rows = ring_rows<R>(w);
+    const size_t lds = (size_t)WAVES * rows * (R + 1) * sizeof(T);
     hipLaunchKernelGGL((sliding_generic_kernel<Op, R, WAVES>), dim3((unsigned)blocks),
-                       dim3(WAVES * kWave), 0, s, static_cast<const T*>(x), n, w,
-                       static_cast<T*>(y), count, total_slabs, spw, vec);
+                       dim3(WAVES * kWave), lds, s, static_cast<const T*>(x), n, w,
+                       static_cast<T*>(y), count, total_slabs, spw, vec, rows);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -302,26 +382,28 @@ static int launch_log(const void* x, uint64_t n, uint32_t w, void* y, uint64_t c
 }
 
 // Elements per lane and waves per workgroup: a window must fit in one slab of
-// 64 * R elements; LDS per wave is the ring of two slabs plus the staging area.
+// 64 * R elements; LDS per wave is the ring of two slab regions plus the
+// repeated rows (the staging area lives in whichever region is free).
 uint32_t generic_max_window() { return kWave * 32; }
 
 // A tile of 4096 outputs plus a halo of w-1 in two LDS buffers stays within 64 KB.
 uint32_t log_max_window() { return 4096; }
 
 int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
-                           hipStream_t s) {
+                           uint64_t tw, hipStream_t s) {
+    // <Op, R, waves per workgroup>
     const bool big = w > (uint32_t)(kWave * 16);
     switch (op) {
-    case kOpAdd: return big ? launch_generic<OpAdd, 32, 1>(x, n, w, y, count, s)
-                            : launch_generic<OpAdd, 16, 2>(x, n, w, y, count, s);
-    case kOpMin: return big ? launch_generic<OpMin, 32, 1>(x, n, w, y, count, s)
-                            : launch_generic<OpMin, 16, 2>(x, n, w, y, count, s);
-    case kOpMax: return big ? launch_generic<OpMax, 32, 1>(x, n, w, y, count, s)
-                            : launch_generic<OpMax, 16, 2>(x, n, w, y, count, s);
+    case kOpAdd: return big ? launch_generic<OpAdd, 32, 1>(x, n, w, y, count, tw, s)
+                            : launch_generic<OpAdd, 16, 2>(x, n, w, y, count, tw, s);
+    case kOpMin: return big ? launch_generic<OpMin, 32, 1>(x, n, w, y, count, tw, s)
+                            : launch_generic<OpMin, 16, 2>(x, n, w, y, count, tw, s);
+    case kOpMax: return big ? launch_generic<OpMax, 32, 1>(x, n, w, y, count, tw, s)
+                            : launch_generic<OpMax, 16, 2>(x, n, w, y, count, tw, s);
     case kOpAffine:
-        if (big) return launch_generic<OpAffine, 32, 1>(x, n, w, y, count, s);
-        if (w > (uint32_t)(kWave * 8)) return launch_generic<OpAffine, 16, 1>(x, n, w, y, count, s);
-        return launch_generic<OpAffine, 8, 2>(x, n, w, y, count, s);
+        if (big) return launch_generic<OpAffine, 32, 1>(x, n, w, y, count, tw, s);
+        if (w > (uint32_t)(kWave * 8)) return launch_generic<OpAffine, 16, 1>(x, n, w, y, count, tw, s);
+        return launch_generic<OpAffine, 8, 2>(x, n, w, y, count, tw, s);
     default: return -2;
     }
 }

@@ -96,4 +96,10 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Index of the calling wavefront in its workgroup, as a wave-uniform (scalar)
+// value, so that loops and branches derived from it stay scalar.
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
 }  // namespace sws

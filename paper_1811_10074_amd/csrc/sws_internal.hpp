@@ -12,8 +12,10 @@ enum { kOpAdd = 0, kOpMin = 1, kOpMax = 2, kOpAffine = 3 };
 // sliding.hip
 uint32_t generic_max_window();
 uint32_t log_max_window();
+// target_waves: wavefronts the launch aims for; each streams
+// ceil(slabs / target_waves) consecutive slabs.
 int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
-                           hipStream_t s);
+                           uint64_t target_waves, hipStream_t s);
 int launch_sliding_log(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
                        hipStream_t s);
 

@@ -81,3 +81,5 @@ def test_minimizer_validation(lib):
     assert lib.sws_minimizers_2bit(ctypes.c_void_p(0x10002), NULL, n, 15, 10, 0, FAKE, FAKE, bound, FAKE, FAKE, 1 << 20, s) == _lib.SWS_ERR_INVALID
     assert lib.sws_set_minimizer_block(0, 100) == _lib.SWS_ERR_INVALID
     assert lib.sws_set_minimizer_block(3, 256) == _lib.SWS_ERR_INVALID
+    assert lib.sws_set_sliding_waves((1 << 24) + 1) == _lib.SWS_ERR_INVALID
+    assert lib.sws_set_sliding_waves(0) == _lib.SWS_OK

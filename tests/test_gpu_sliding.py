@@ -167,3 +167,56 @@ def test_config3_full_size_sampled(op):
                 exp = ((pfx[w:] - pfx[:-w]) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
                 assert np.array_equal(yh, exp), w
                 del pfx, exp
+
+
+def _slab(op, w):
+    """Elements per wavefront slab of the generic kernel for (op, w)."""
+    if op == "affine":
+        r = 8 if w <= 512 else (16 if w <= 1024 else 32)
+    else:
+        r = 16 if w <= 1024 else 32
+    return 64 * r
+
+
+@pytest.fixture
+def few_waves():
+    import paper_1811_10074_amd as sws
+    yield sws.set_sliding_waves
+    sws.set_sliding_waves(0)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 3])
+@pytest.mark.parametrize("op", ["add", "min", "max", "affine"])
+def test_long_streams_per_wave(few_waves, waves, op):
+    """Few wavefronts, each streaming many slabs: the unchecked steady-state
+    loop, its peeled first step, the last in-range step of a wave and the
+    checked steps at the end, with n on either side of the slab boundaries
+    that decide between them."""
+    torch = torch_cuda()
+    few_waves(waves)
+    seed = {"add": 21, "min": 22, "max": 23, "affine": 24}[op]
+    for w in (1, 16, 17, 1024, 1025, 2048):
+        S = _slab(op, w)
+        for n in (3 * S - 1, 3 * S + w - 1, 4 * S + w, 5 * S + w - 2, 7 * S + w + 1):
+            if n < w:
+                continue
+            x = inputs.affine_pairs(n, seed + n, odd=True) if op == "affine" else \
+                inputs.uniform_u32(n, seed + n)
+            check(torch, op, w, x, "generic")
+
+
+@pytest.mark.parametrize("waves", [1, 3])
+def test_long_streams_unaligned(few_waves, waves):
+    """As above on views 1..3 elements into a buffer (the checked path for
+    every step)."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    few_waves(waves)
+    base = inputs.uniform_u32(9 * S16 + 77, 31)
+    t = dev(base, torch)
+    for off in (0, 1, 3):
+        for w in (16, 300):
+            for op in ("add", "max"):
+                y = sws.sliding_sum(op, w, t[off:], path="generic")
+                torch.cuda.synchronize()
+                assert np.array_equal(host_u32(y), oracle.sliding_sum(op, w, base[off:])), (off, w, op)
