@@ -357,14 +357,21 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v, int lane) {
     return v;
 }
 
-// Exclusive prefix of the tile's store count over the tiles before it
-// (decoupled look-back, one wavefront).  Each tile first publishes its own
-// count (AGGREGATE), then reads the status words of the 64 tiles before it in
-// one round: if every tile back to the nearest one with an INCLUSIVE prefix
-// has published, their counts plus that prefix give the answer; otherwise it
-// waits and re-reads.  Without an INCLUSIVE word among the 64 it moves 64
-// further back.  Called by all 64 lanes of one wave; returns the prefix in
-// every lane.
+// Exclusive prefix of a look-back participant's store count over the
+// participants before it (decoupled look-back, one wavefront).  Each first
+// publishes its own count (AGGREGATE), then reads the status words of the 64
+// participants before it in one round: if every one back to the nearest with
+// an INCLUSIVE prefix has published, their counts plus that prefix give the
+// answer; otherwise it waits and re-reads.  Without an INCLUSIVE word among
+// the 64 it moves 64 further back.  Called by all 64 lanes of one wave;
+// returns the prefix in every lane.
+//
+// Status words sit one per 64-byte line (kStatusStride words apart): the
+// words of neighbouring participants are written and polled by different
+// compute units at device scope, and sharing a line serializes those
+// accesses.  The status traffic and the distance to the nearest INCLUSIVE
+// word both grow with the number of participants, so the w <= 32 path makes
+// a workgroup of wave tiles one participant.
 __device__ uint64_t tile_lookback(uint64_t* status, uint64_t tile, uint64_t total, uint32_t* err,
                                   int lane) {
     const uint64_t kAgg = 1ull << 62, kInc = 2ull << 62, kVal = (1ull << 62) - 1ull;
@@ -374,15 +381,16 @@ __device__ uint64_t tile_lookback(uint64_t* status, uint64_t tile, uint64_t tota
         return 0;
     }
     if (lane == 0)
-        __hip_atomic_store(&status[tile], kAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&status[tile * kStatusStride], kAgg | total, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     uint64_t excl = 0;
     int64_t base = (int64_t)tile - 1;
     uint32_t spins = 0;
     for (;;) {
         const int64_t j = base - lane;
-        // before tile 0 there is nothing: read as an INCLUSIVE prefix of 0
-        const uint64_t s = j >= 0 ? __hip_atomic_load(&status[j], __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT)
+        // before participant 0 there is nothing: read as an INCLUSIVE prefix of 0
+        const uint64_t s = j >= 0 ? __hip_atomic_load(&status[(uint64_t)j * kStatusStride],
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                   : kInc;
         const uint64_t f = s >> 62;
         const uint64_t inc = __ballot(f == 2);
@@ -407,7 +415,7 @@ __device__ uint64_t tile_lookback(uint64_t* status, uint64_t tile, uint64_t tota
         base -= kWave;
     }
     if (lane == 0)
-        __hip_atomic_store(&status[tile], kInc | (excl + total), __ATOMIC_RELAXED,
+        __hip_atomic_store(&status[tile * kStatusStride], kInc | (excl + total), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     return excl;
 }
@@ -647,31 +655,38 @@ __device__ __forceinline__ void doubling_shift(Key (&m)[kR], int lane, uint32_t 
 template <int NT, int IN, bool KM64, bool FULL, int FLAGS>
 __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, MinimizerArgs a) {
     constexpr int NWV = NT / kWave;
+    static_assert(NWV <= kWave, "one lane per wave of the workgroup");
     __shared__ uint32_t s_code[NWV][kWaveWords], s_inv[NWV][kWaveWords];
+    __shared__ uint32_t s_cnt[NWV];  // stores per wave tile
+    __shared__ uint64_t s_base;      // stores before the workgroup
 
     const int lane = lane_id();
-    const int wv = (int)(threadIdx.x >> 6);
+    const int wv = wave_id();
     const uint32_t w = a.w;
     uint32_t* code = s_code[wv];
     uint32_t* inv = s_inv[wv];
 
-    // Tile order = workgroup order.  A tile waits (look-back) only for tiles
-    // of lower index, which belong to workgroups dispatched before it; the
-    // lowest unfinished tile never waits, so every tile finishes.
+    // Tile order = workgroup order.  The workgroup's wave tiles are
+    // consecutive; their counts are added in LDS and one wave does the
+    // look-back for the workgroup, which waits only for workgroups dispatched
+    // before it, so the lowest unfinished one never waits and every one
+    // finishes.  (One look-back per workgroup rather than per wave: the status
+    // words are read through to memory, and their traffic and the distance to
+    // the nearest inclusive prefix both grow with the number of participants.)
     const uint64_t cur = (uint64_t)blockIdx.x * NWV + (uint64_t)wv;
-    if (cur >= a.ntiles) return;
-    RawWords raw;
-    fetch_words<IN>(in, (int64_t)(cur * a.tw) - 16, lane, raw);
-    {
-        const int64_t p0 = (int64_t)(cur * a.tw);
-        const int64_t K0 = p0 - 16;
-
-        // 1. bases (loaded during the previous tile)
+    const bool have = cur < a.ntiles;  // waves past the last tile only join the barriers
+    const int64_t p0 = (int64_t)(cur * a.tw);
+    const int64_t K0 = p0 - 16;
+    Key m[kR];
+    uint32_t emit = 0;
+    if (have) {
+        RawWords raw;
+        fetch_words<IN>(in, K0, lane, raw);
+        // 1. bases
         commit_words<IN>(in, K0, lane, raw, code, inv);
         wave_lds_sync();
 
         // 2. keys
-        Key m[kR];
         {
             uint64_t val[kR];
             uint32_t bad;
@@ -697,7 +712,6 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
         doubling_shift<FULL>(m, lane, w - L);  // 0 <= w - L < L <= 32
 
         // 4. dedup: window j is stored iff owned, valid and at a new position
-        uint32_t emit = 0;
         {
             uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
 #pragma unroll
@@ -711,18 +725,32 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
                 prev = m[e].tag;
             }
         }
+    }
 
-        // 5. ordered compaction: lane prefix, look-back, stores from registers
-        const uint32_t cnt = (uint32_t)__builtin_popcount(emit);
-        uint32_t incl = cnt;
+    // 5. ordered compaction: lane prefix, workgroup sum, look-back, stores
+    //    from registers
+    const uint32_t cnt = (uint32_t)__builtin_popcount(emit);
+    uint32_t incl = cnt;
 #pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t o = shfl(incl, lane, -d);
-            if (lane >= d) incl += o;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = shfl(incl, lane, -d);
+        if (lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) s_cnt[wv] = incl;
+    __syncthreads();
+    if (wv == 0) {
+        const uint32_t c = lane < NWV ? s_cnt[lane] : 0u;
+        const uint64_t block_total = lane_value_u64(wave_sum_u64(c, lane), 0);
+        const uint64_t ex = tile_lookback(a.status, blockIdx.x, block_total, a.err, lane);
+        if (lane == 0) {
+            s_base = ex;
+            if (blockIdx.x == gridDim.x - 1) *a.d_count = final_count(a.err, ex + block_total);
         }
-        const uint32_t total = lane_value(incl, kWave - 1);
-        const uint64_t excl = tile_lookback(a.status, cur, total, a.err, lane);
-        uint64_t g = excl + (incl - cnt);
+    }
+    __syncthreads();
+    if (have) {
+        uint64_t g = s_base + (incl - cnt);
+        for (int v = 0; v < wv; ++v) g += s_cnt[v];
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
             if ((emit >> e) & 1u) {
@@ -733,7 +761,6 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
                 ++g;
             }
         }
-        if (lane == 0 && cur == a.ntiles - 1) *a.d_count = final_count(a.err, excl + total);
     }
 }
 
@@ -791,9 +818,11 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     __shared__ uint32_t s_rid[NWV][kTileRange + 1];
     __shared__ uint32_t s_rstart[NWV][kTileRange + 1];
     __shared__ uint32_t s_lexcl[NWV][kWave], s_lemit[NWV][kWave];
+    __shared__ uint32_t s_cnt[NWV];  // stores per wave tile
+    __shared__ uint64_t s_base;      // stores before the workgroup
 
     const int lane = lane_id();
-    const int wv = (int)(threadIdx.x >> 6);
+    const int wv = wave_id();
     const uint32_t w = a.w, k = a.k;
     uint32_t* code = s_code[wv];
     uint32_t* inv = s_inv[wv];
@@ -801,116 +830,136 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     uint32_t* rid = s_rid[wv];
     uint32_t* rstart = s_rstart[wv];
 
+    // the workgroup's wave tiles are one look-back participant (as in
+    // minimizer_wave_kernel)
     const uint64_t cur = (uint64_t)blockIdx.x * NWV + (uint64_t)wv;
-    if (cur >= a.ntiles) return;
+    const bool has_tile = cur < a.ntiles;  // waves past the last tile only join the barriers
     const int64_t p0 = (int64_t)(cur * a.tw);
     const int64_t K0 = p0 - 16;
-    RawWords raw;
-    fetch_words<kInAscii>(in, K0, lane, raw);
-
-    // read boundaries of [K0, K0 + kTileRange)
-    for (int i = lane; i < kBitmapWords; i += kWave) bits[i] = 0u;
-    wave_lds_sync();
-    const int64_t rng_end = K0 + kTileRange;
-    const uint32_t r0 = a.first_read[cur];
-    uint32_t listed = 0;
-    uint32_t pre = 0;  // the first listed read starts before the tile
-    for (uint64_t base_r = r0;; base_r += kWave) {
-        const uint64_t r = base_r + (uint64_t)lane;
-        const bool have = r < a.nreads;
-        const int64_t rs = have ? (int64_t)a.offsets[r] : (int64_t)a.total;
-        const int64_t re = have ? (int64_t)a.offsets[r + 1] : (int64_t)a.total;
-        const bool take = have && re > rs && re > K0 && rs < rng_end;
-        const uint64_t tmask = __ballot(take);
-        if (take) {
-            const uint32_t idx = listed + (uint32_t)__builtin_popcountll(tmask & ((1ull << lane) - 1ull));
-            if (idx <= (uint32_t)kTileRange) {
-                rid[idx] = (uint32_t)r;
-                rstart[idx] = (uint32_t)rs;
-            }
-            if (rs >= K0) {
-                const uint32_t b = (uint32_t)(rs - K0);
-                atomicOr(&bits[b >> 5], 1u << (b & 31));
-            } else {
-                pre = 1;
-            }
-        }
-        listed += (uint32_t)__builtin_popcountll(tmask);
-        if (__ballot(!have || rs >= rng_end)) break;
-    }
-    pre = __ballot(pre != 0) ? 1u : 0u;
-    if (lane == 0 && (int64_t)a.total >= K0 && (int64_t)a.total < rng_end) {
-        const uint32_t b = (uint32_t)((int64_t)a.total - K0);  // end of the last read
-        atomicOr(&bits[b >> 5], 1u << (b & 31));
-    }
-    wave_lds_sync();
-    // this lane's 64 boundary bits from tile position 16 * lane
-    uint64_t B;
-    {
-        const uint32_t wi = (uint32_t)lane >> 1;
-        const uint64_t W = (uint64_t)bits[wi] | ((uint64_t)bits[wi + 1] << 32);
-        B = (lane & 1) ? ((W >> 16) | ((uint64_t)bits[wi + 2] << 48)) : W;
-    }
-    const uint32_t kcross = or_after(B, k - 1u);      // k-mer e spans a read start
-    const uint32_t wcross = or_after(B, k + w - 2u);  // window e spans a read start
-
-    // bases and keys
-    commit_words<kInAscii>(in, K0, lane, raw, code, inv);
-    wave_lds_sync();
+    uint32_t r0 = 0, pre = 0, emit = 0, cnt = 0, incl = 0, sincl = 0, starts = 0;
+    uint64_t B = 0;
     Key m[kR];
-    {
-        uint64_t val[kR];
-        uint32_t bad;
-        lane_kmers<KM64, FLAGS>(code, inv, lane, k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u,
-                                val, bad);
-        bad |= kcross;
-#pragma unroll
-        for (int e = 0; e < kR; ++e) {
-            const bool iv = (bad >> e) & 1u;
-            m[e].lo = iv ? 0xFFFFFFFFu : (uint32_t)val[e];
-            m[e].hi = iv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
-            m[e].tag = ((uint32_t)lane * kR + e) | (iv ? kInvalidTag : 0u);
-        }
-    }
-    uint32_t L = 1;
-    if (2u <= w) { doubling_step<1, FULL>(m, lane); L = 2; }
-    if (4u <= w) { doubling_step<2, FULL>(m, lane); L = 4; }
-    if (8u <= w) { doubling_step<4, FULL>(m, lane); L = 8; }
-    if (16u <= w) { doubling_step<8, FULL>(m, lane); L = 16; }
-    if (32u <= w) { doubling_step<16, FULL>(m, lane); L = 32; }
-    doubling_shift<FULL>(m, lane, w - L);
+    if (has_tile) {
+        RawWords raw;
+        fetch_words<kInAscii>(in, K0, lane, raw);
 
-    // dedup, restarting at read starts
-    uint32_t emit = 0;
-    {
-        uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
-#pragma unroll
-        for (int e = 0; e < kR; ++e) {
-            const uint32_t j = (uint32_t)lane * kR + e;
-            const int64_t p = K0 + (int64_t)j;
-            const bool owned = j >= 16u && j < 16u + a.tw && p < (int64_t)a.total;
-            const bool valid = (m[e].tag & kInvalidTag) == 0u && !((wcross >> e) & 1u);
-            const bool fresh = ((B >> e) & 1u) || m[e].tag != prev;
-            emit |= (owned && valid && fresh ? 1u : 0u) << e;
-            prev = m[e].tag;
+        // read boundaries of [K0, K0 + kTileRange)
+        for (int i = lane; i < kBitmapWords; i += kWave) bits[i] = 0u;
+        wave_lds_sync();
+        const int64_t rng_end = K0 + kTileRange;
+        r0 = a.first_read[cur];
+        uint32_t listed = 0;  // pre: the first listed read starts before the tile
+        for (uint64_t base_r = r0;; base_r += kWave) {
+            const uint64_t r = base_r + (uint64_t)lane;
+            const bool have = r < a.nreads;
+            const int64_t rs = have ? (int64_t)a.offsets[r] : (int64_t)a.total;
+            const int64_t re = have ? (int64_t)a.offsets[r + 1] : (int64_t)a.total;
+            const bool take = have && re > rs && re > K0 && rs < rng_end;
+            const uint64_t tmask = __ballot(take);
+            if (take) {
+                const uint32_t idx = listed + (uint32_t)__builtin_popcountll(tmask & ((1ull << lane) - 1ull));
+                if (idx <= (uint32_t)kTileRange) {
+                    rid[idx] = (uint32_t)r;
+                    rstart[idx] = (uint32_t)rs;
+                }
+                if (rs >= K0) {
+                    const uint32_t b = (uint32_t)(rs - K0);
+                    atomicOr(&bits[b >> 5], 1u << (b & 31));
+                } else {
+                    pre = 1;
+                }
+            }
+            listed += (uint32_t)__builtin_popcountll(tmask);
+            if (__ballot(!have || rs >= rng_end)) break;
         }
-    }
-    const uint32_t cnt = (uint32_t)__builtin_popcount(emit);
-    const uint32_t starts = (uint32_t)__builtin_popcountll(B & 0xFFFFull);
-    uint32_t incl = cnt, sincl = starts;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t o = shfl(incl, lane, -d);
-        const uint32_t so = shfl(sincl, lane, -d);
-        if (lane >= d) {
-            incl += o;
-            sincl += so;
+        pre = __ballot(pre != 0) ? 1u : 0u;
+        if (lane == 0 && (int64_t)a.total >= K0 && (int64_t)a.total < rng_end) {
+            const uint32_t b = (uint32_t)((int64_t)a.total - K0);  // end of the last read
+            atomicOr(&bits[b >> 5], 1u << (b & 31));
         }
+        wave_lds_sync();
+        // this lane's 64 boundary bits from tile position 16 * lane
+        {
+            const uint32_t wi = (uint32_t)lane >> 1;
+            const uint64_t W = (uint64_t)bits[wi] | ((uint64_t)bits[wi + 1] << 32);
+            B = (lane & 1) ? ((W >> 16) | ((uint64_t)bits[wi + 2] << 48)) : W;
+        }
+        const uint32_t kcross = or_after(B, k - 1u);      // k-mer e spans a read start
+        const uint32_t wcross = or_after(B, k + w - 2u);  // window e spans a read start
+
+        // bases and keys
+        commit_words<kInAscii>(in, K0, lane, raw, code, inv);
+        wave_lds_sync();
+        {
+            uint64_t val[kR];
+            uint32_t bad;
+            lane_kmers<KM64, FLAGS>(code, inv, lane, k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u,
+                                    val, bad);
+            bad |= kcross;
+#pragma unroll
+            for (int e = 0; e < kR; ++e) {
+                const bool iv = (bad >> e) & 1u;
+                m[e].lo = iv ? 0xFFFFFFFFu : (uint32_t)val[e];
+                m[e].hi = iv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
+                m[e].tag = ((uint32_t)lane * kR + e) | (iv ? kInvalidTag : 0u);
+            }
+        }
+        uint32_t L = 1;
+        if (2u <= w) { doubling_step<1, FULL>(m, lane); L = 2; }
+        if (4u <= w) { doubling_step<2, FULL>(m, lane); L = 4; }
+        if (8u <= w) { doubling_step<4, FULL>(m, lane); L = 8; }
+        if (16u <= w) { doubling_step<8, FULL>(m, lane); L = 16; }
+        if (32u <= w) { doubling_step<16, FULL>(m, lane); L = 32; }
+        doubling_shift<FULL>(m, lane, w - L);
+
+        // dedup, restarting at read starts
+        {
+            uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
+#pragma unroll
+            for (int e = 0; e < kR; ++e) {
+                const uint32_t j = (uint32_t)lane * kR + e;
+                const int64_t p = K0 + (int64_t)j;
+                const bool owned = j >= 16u && j < 16u + a.tw && p < (int64_t)a.total;
+                const bool valid = (m[e].tag & kInvalidTag) == 0u && !((wcross >> e) & 1u);
+                const bool fresh = ((B >> e) & 1u) || m[e].tag != prev;
+                emit |= (owned && valid && fresh ? 1u : 0u) << e;
+                prev = m[e].tag;
+            }
+        }
+        cnt = (uint32_t)__builtin_popcount(emit);
+        starts = (uint32_t)__builtin_popcountll(B & 0xFFFFull);
+        incl = cnt;
+        sincl = starts;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = shfl(incl, lane, -d);
+            const uint32_t so = shfl(sincl, lane, -d);
+            if (lane >= d) {
+                incl += o;
+                sincl += so;
+            }
+        }
+        s_lexcl[wv][lane] = incl - cnt;
+        s_lemit[wv][lane] = emit;
     }
+
     const uint32_t total = lane_value(incl, kWave - 1);
-    s_lexcl[wv][lane] = incl - cnt;
-    s_lemit[wv][lane] = emit;
-    const uint64_t excl = tile_lookback(a.status, cur, total, a.err, lane);
+    if (lane == 0) s_cnt[wv] = total;
+    __syncthreads();
+    if (wv == 0) {
+        const uint32_t c = lane < NWV ? s_cnt[lane] : 0u;
+        const uint64_t block_total = lane_value_u64(wave_sum_u64(c, lane), 0);
+        const uint64_t ex = tile_lookback(a.status, blockIdx.x, block_total, a.err, lane);
+        if (lane == 0) {
+            s_base = ex;
+            if (blockIdx.x == gridDim.x - 1)
+                a.read_out[a.nreads] = final_count(a.err, ex + block_total);
+        }
+    }
+    __syncthreads();
+    if (!has_tile) return;  // no barrier follows
+    uint64_t excl = s_base;
+    for (int v = 0; v < wv; ++v) excl += s_cnt[v];
     // read rank of position e: listed reads starting at or before it, minus one
     const int32_t rank0 = (int32_t)(pre + sincl - starts) - 1;
     uint64_t g = excl + (incl - cnt);
@@ -946,7 +995,6 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
         }
         if (__ballot(!have || rs >= own_end)) break;
     }
-    if (last && lane == 0) a.read_out[a.nreads] = final_count(a.err, excl + total);
 }
 
 __global__ void zero_words_kernel(uint64_t* __restrict__ p, uint64_t count) {
@@ -1012,8 +1060,9 @@ int launch_minimizers_batch(const GenomeInput& in, BatchArgs a, uint32_t nt, voi
     uint8_t* ws = static_cast<uint8_t*>(workspace);
     a.err = reinterpret_cast<uint32_t*>(ws + 8);
     a.status = reinterpret_cast<uint64_t*>(ws + kWsStatusOffset);
-    a.first_read = reinterpret_cast<uint32_t*>(ws + kWsStatusOffset + 8 * a.ntiles);
-    if (launch_zero(reinterpret_cast<uint64_t*>(ws), kWsStatusOffset / 8 + a.ntiles, s) != 0)
+    a.first_read = reinterpret_cast<uint32_t*>(ws + kWsStatusOffset + 8 * kStatusStride * a.ntiles);
+    if (launch_zero(reinterpret_cast<uint64_t*>(ws), kWsStatusOffset / 8 + kStatusStride * a.ntiles,
+                    s) != 0)
         return -1;
     const uint64_t rb = ((uint64_t)a.nreads + 255) / 256;
     hipLaunchKernelGGL(batch_first_read_kernel, dim3((unsigned)(rb < 4096 ? (rb ? rb : 1) : 4096)),
@@ -1036,7 +1085,9 @@ int launch_minimizers_batch(const GenomeInput& in, BatchArgs a, uint32_t nt, voi
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-uint64_t batch_workspace_bytes(uint64_t ntiles) { return kWsStatusOffset + 12ull * ntiles; }
+uint64_t batch_workspace_bytes(uint64_t ntiles) {
+    return kWsStatusOffset + (8ull * kStatusStride + 4ull) * ntiles;
+}
 
 uint32_t batch_tile_windows(uint32_t w) { return minimizer_tile_windows(kWave, w); }
 
@@ -1055,7 +1106,9 @@ uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t w) {
                                             : minimizer_tile_windows(nt, w);
 }
 
-uint64_t minimizer_workspace_bytes(uint64_t ntiles) { return kWsStatusOffset + 8ull * ntiles; }
+uint64_t minimizer_workspace_bytes(uint64_t ntiles) {
+    return kWsStatusOffset + 8ull * kStatusStride * ntiles;
+}
 
 template <int NT, int IN, bool KM64, bool FULL>
 static void launch_wave_variant(const GenomeInput& in, const MinimizerArgs& a, hipStream_t s) {
@@ -1096,13 +1149,19 @@ int launch_minimizers(const GenomeInput& in, MinimizerArgs a, uint32_t nt, void*
     a.counter = reinterpret_cast<uint64_t*>(ws);
     a.err = reinterpret_cast<uint32_t*>(ws + 8);
     a.status = reinterpret_cast<uint64_t*>(ws + kWsStatusOffset);
-    if (launch_zero(reinterpret_cast<uint64_t*>(ws), kWsStatusOffset / 8 + a.ntiles, s) != 0)
+    // one status word per look-back participant: a workgroup of wave tiles on
+    // the w <= 32 path, a tile (= workgroup) otherwise
+    const bool wave_path = a.w <= minimizer_wave_max_window();
+    const uint64_t parts = wave_path ? (a.ntiles + kWaveTileGroup - 1) / kWaveTileGroup : a.ntiles;
+    if (launch_zero(reinterpret_cast<uint64_t*>(ws), kWsStatusOffset / 8 + kStatusStride * parts,
+                    s) != 0)
         return -1;
     const bool km64 = a.k > 16;
     const bool full = a.k >= 30 && (a.flags & 2u) == 0u;
-    if (a.w <= minimizer_wave_max_window()) {
-        if (in.kind == kInAscii) launch_min_wave<256, kInAscii>(in, a, km64, full, s);
-        else launch_min_wave<256, kIn2bit>(in, a, km64, full, s);
+    if (wave_path) {
+        constexpr int NT = kWaveTileGroup * kWave;
+        if (in.kind == kInAscii) launch_min_wave<NT, kInAscii>(in, a, km64, full, s);
+        else launch_min_wave<NT, kIn2bit>(in, a, km64, full, s);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     if (in.kind == kInAscii) {
