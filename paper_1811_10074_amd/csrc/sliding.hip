@@ -92,6 +92,27 @@ struct SlabIO {
         }
     }
 
+    // Chunks below nchunks of the slab at element p0 (wholly below n), the
+    // rest as the identity: the slab after a wave's last one is needed only
+    // up to its first w - 1 elements.
+    static __device__ __forceinline__ void load_head(const T* __restrict__ x, uint64_t p0, int lane,
+                                                     uint32_t nchunks, T ident,
+                                                     u32x4 (&raw)[kChunks]) {
+        const uint64_t per = 16 / sizeof(T);
+        const uint32_t* iw = reinterpret_cast<const uint32_t*>(&ident);
+        constexpr int wpe = (int)(sizeof(T) / 4);
+        u32x4 id;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) id[q] = iw[q % wpe];
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const uint32_t c = (uint32_t)(i * kWave + lane);
+            raw[i] = c < nchunks ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(
+                                       x + p0 + (uint64_t)c * per))
+                                 : id;
+        }
+    }
+
     // raw chunks -> this lane's run, through the staging area
     static __device__ __forceinline__ void to_run(uint32_t* stage, int lane,
                                                   const u32x4 (&raw)[kChunks], T (&v)[R]) {
@@ -183,6 +204,7 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
     const uint64_t s1 = s0 + slabs_per_wave < total_slabs ? s0 + slabs_per_wave : total_slabs;
 
     const uint32_t span = (w + R - 1) / R;
+    const uint32_t head_chunks = (uint32_t)(((w - 1u) * sizeof(T) + 15u) / 16u);  // first w - 1 elements
     const uint32_t mirror = (R + w - 2u) / R;  // rows of region 0 repeated from row 128
     const uint32_t lane_row = (uint32_t)lane * RS;
     const uint32_t lane_mod = (uint32_t)(((uint64_t)lane * R) % w);
@@ -213,13 +235,18 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
         slab_suffix<Op, R>(sfA, headsA, span, lane);
         heads_to_identity<R>(sfA, headsA, ident);
     }
-    IO::template load<true>(x, n, (s0 + 1) * S, lane, v16, ident, raw);  // slab B
+    // slab B; when it is the next wave's first slab, only its first w - 1
+    // elements enter this wave's outputs
+    const uint64_t halo_n = s1 * (uint64_t)S + w - 1u < n ? s1 * (uint64_t)S + w - 1u : n;
+    IO::template load<true>(x, s0 + 1 == s1 ? halo_n : n, (s0 + 1) * S, lane, v16, ident, raw);
     uint32_t half = 0;  // ring half holding slab A's prefix sums
 
     // One step: slab A = s gets its outputs, slab B = s + 1 (in raw) becomes A.
     // MODE 0: every access in range and slab s + 2 is loaded into raw;
     // MODE 1: every access in range, nothing left to load (the last slab of
-    // the wave); MODE 2: accesses checked against n and count.
+    // the wave); MODE 2: accesses checked against n and count; MODE 3: as
+    // MODE 0 with slab s + 2 the next wave's first, of which only the first
+    // w - 1 elements are loaded.
     auto step = [&](uint64_t s, auto mode) {
         constexpr int MODE = decltype(mode)::value;
         constexpr bool CHECK = MODE == 2;
@@ -232,8 +259,13 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
             T v[R];
             IO::to_run(stage_of(half ^ 1u), lane, raw, v);  // B's region is free
             // prefetch slab s + 2 while B and A are computed
-            if (MODE == 0 || (MODE == 2 && s + 1 < s1))
-                IO::template load<CHECK>(x, n, baseA + 2 * (uint64_t)S, lane, v16, ident, raw);
+            if (MODE == 0)
+                IO::template load<false>(x, n, baseA + 2 * (uint64_t)S, lane, v16, ident, raw);
+            else if (MODE == 3)
+                IO::load_head(x, baseA + 2 * (uint64_t)S, lane, head_chunks, ident, raw);
+            else if (MODE == 2 && s + 1 < s1)
+                IO::template load<true>(x, s + 2 == s1 ? halo_n : n, baseA + 2 * (uint64_t)S,
+                                        lane, v16, ident, raw);
             uint32_t m0 = mB + lane_mod;
             m0 = m0 >= w ? m0 - w : m0;
             headsB = lane_heads<R>(m0, w, pat);
@@ -294,6 +326,7 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
     using M0 = std::integral_constant<int, 0>;
     using M1 = std::integral_constant<int, 1>;
     using M2 = std::integral_constant<int, 2>;
+    using M3 = std::integral_constant<int, 3>;
     const uint64_t by_count = count / S;  // s + 1 <= count / S: outputs in range
     uint64_t s = s0;
     if (v16) {
@@ -301,8 +334,13 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
         uint64_t pf_end = by_n < by_count ? by_n : by_count;
         if (pf_end > s1 - 1) pf_end = s1 - 1;
         if (s < pf_end) {
-            step(s++, M0());
-            for (; s < pf_end; ++s) step(s, M0());
+            // pf_end <= s1 - 1; the step s1 - 2 prefetches the next wave's slab
+            const uint64_t full_end = pf_end == s1 - 1 ? s1 - 2 : pf_end;
+            if (s < full_end) {
+                step(s++, M0());
+                for (; s < full_end; ++s) step(s, M0());
+            }
+            if (s < pf_end) step(s++, M3());
         }
     }
     for (; s < s1; ++s) {
