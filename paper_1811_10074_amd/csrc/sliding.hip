@@ -352,37 +352,104 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
 // ---------------------------------------------------------------------------
 // Log path (MIN / MAX).
 // ---------------------------------------------------------------------------
+// LDS index of tile position i: one pad word per 16, so that threads reading
+// runs of 16 consecutive positions (one run per thread) hit distinct banks.
+__device__ __forceinline__ uint32_t log_pad(uint32_t i) { return i + (i >> 4); }
+
+constexpr int kLogRun = 16;  // positions per thread run in the register levels
+
+// One doubling level on a register window: v[e] = v[e] (+) v[e + S].
+template <class Op, int S, int N>
+__device__ __forceinline__ void log_level(uint32_t (&v)[N]) {
+#pragma unroll
+    for (int e = 0; e + S < N; ++e) v[e] = Op::combine(v[e], v[e + S]);
+}
+
 template <class Op, int NT>
 __global__ __launch_bounds__(NT) void sliding_log_kernel(const uint32_t* __restrict__ x, uint64_t n,
                                                          uint32_t w, uint32_t* __restrict__ y,
-                                                         uint64_t count, uint32_t tile) {
+                                                         uint64_t count, uint32_t tile, int vec) {
+    constexpr int RR = kLogRun;
     extern __shared__ uint32_t lds[];
-    const uint32_t L = tile + w - 1u;
+    const uint32_t L = tile + w - 1u;           // tile plus its halo
     uint32_t* bufA = lds;
-    uint32_t* bufB = lds + L;
+    uint32_t* bufB = lds + log_pad(L) + 1u;
     const uint64_t t0 = (uint64_t)blockIdx.x * tile;
-    for (uint32_t i = threadIdx.x; i < L; i += NT) {
+    // load the tile and halo; aligned 16-byte chunks wholly below n take one
+    // vector load each (t0 is a multiple of 4, a chunk never crosses a pad)
+    const uint32_t nv = vec ? L / 4u : 0u;
+    for (uint32_t c = threadIdx.x; c < nv; c += NT) {
+        const uint64_t g = t0 + 4u * c;
+        u32x4 q;
+        if (g + 4u <= n) {
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(x + g));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = g + k < n ? x[g + k] : Op::identity();
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bufA[log_pad(4u * c + k)] = q[k];
+    }
+    for (uint32_t i = 4u * nv + threadIdx.x; i < L; i += NT) {
         const uint64_t g = t0 + i;
-        bufA[i] = g < n ? x[g] : Op::identity();
+        bufA[log_pad(i)] = g < n ? x[g] : Op::identity();
     }
     __syncthreads();
-    uint32_t p2 = 1;
+    uint32_t p2 = 1;  // largest power of two not above w
     while (p2 * 2u <= w) p2 *= 2u;
-    uint32_t* src = bufA;
-    uint32_t* dst = bufB;
-    for (uint32_t s = 1; s < p2; s *= 2u) {
-        // windows of 2s: positions [0, L - 2s + 1)
+    // Levels with shifts below RR in registers: a thread takes a run of RR
+    // positions plus the RR - 1 after it and leaves m^(Q) of its run in bufB,
+    // Q = min(p2, RR), on the positions [0, L - Q + 1) later levels read.
+    const uint32_t q = p2 < (uint32_t)RR ? p2 : (uint32_t)RR;
+    const uint32_t nq = L - q + 1u;
+    for (uint32_t j = threadIdx.x; j * RR < nq; j += NT) {
+        uint32_t v[2 * RR];
+#pragma unroll
+        for (int e = 0; e < 2 * RR; ++e) {
+            const uint32_t p = j * RR + (uint32_t)e;
+            v[e] = p < L ? bufA[log_pad(p)] : Op::identity();
+        }
+        if (q > 1u) log_level<Op, 1>(v);
+        if (q > 2u) log_level<Op, 2>(v);
+        if (q > 4u) log_level<Op, 4>(v);
+        if (q > 8u) log_level<Op, 8>(v);
+#pragma unroll
+        for (int e = 0; e < RR; ++e) {
+            const uint32_t p = j * RR + (uint32_t)e;
+            if (p < nq) bufB[log_pad(p)] = v[e];
+        }
+    }
+    __syncthreads();
+    // Levels with shifts of RR and more through LDS: windows of 2s on the
+    // positions [0, L - 2s + 1).
+    uint32_t* src = bufB;
+    uint32_t* dst = bufA;
+    for (uint32_t s = q; s < p2; s *= 2u) {
         const uint32_t len = L - 2u * s + 1u;
-        for (uint32_t i = threadIdx.x; i < len; i += NT) dst[i] = Op::combine(src[i], src[i + s]);
+        for (uint32_t i = threadIdx.x; i < len; i += NT)
+            dst[log_pad(i)] = Op::combine(src[log_pad(i)], src[log_pad(i + s)]);
         __syncthreads();
         uint32_t* t = src;
         src = dst;
         dst = t;
     }
     const uint32_t shift = w - p2;
-    for (uint32_t i = threadIdx.x; i < tile; i += NT) {
-        const uint64_t g = t0 + i;
-        if (g < count) y[g] = Op::combine(src[i], src[i + shift]);
+    // outputs four at a time, one 16-byte store per full aligned chunk
+    for (uint32_t c = threadIdx.x; 4u * c < tile; c += NT) {
+        const uint64_t g = t0 + 4u * c;
+        u32x4 r;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = 4u * c + k;
+            r[k] = Op::combine(src[log_pad(i)], src[log_pad(i + shift)]);
+        }
+        if (vec && g + 4u <= count) {
+            __builtin_nontemporal_store(r, reinterpret_cast<u32x4*>(y + g));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (g + k < count) y[g + k] = r[k];
+        }
     }
 }
 
@@ -411,11 +478,15 @@ static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64
 template <class Op>
 static int launch_log(const void* x, uint64_t n, uint32_t w, void* y, uint64_t count, hipStream_t s) {
     constexpr int NT = 256;
-    const uint32_t tile = 4096;
-    const size_t lds = 2ull * (tile + w - 1ull) * sizeof(uint32_t);
+    // two padded buffers of tile + w - 1 words within 64 KB
+    const uint32_t tile = w <= 2048u ? 4096u : 2048u;
+    const uint64_t L = tile + w - 1ull;
+    const size_t lds = 2ull * (L + L / 16 + 1ull) * sizeof(uint32_t);
     const uint64_t blocks = (count + tile - 1) / tile;
+    const int vec = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0 ? 1 : 0;
     hipLaunchKernelGGL((sliding_log_kernel<Op, NT>), dim3((unsigned)blocks), dim3(NT), lds, s,
-                       static_cast<const uint32_t*>(x), n, w, static_cast<uint32_t*>(y), count, tile);
+                       static_cast<const uint32_t*>(x), n, w, static_cast<uint32_t*>(y), count, tile,
+                       vec);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -424,7 +495,8 @@ static int launch_log(const void* x, uint64_t n, uint32_t w, void* y, uint64_t c
 // repeated rows (the staging area lives in whichever region is free).
 uint32_t generic_max_window() { return kWave * 32; }
 
-// A tile of 4096 outputs plus a halo of w-1 in two LDS buffers stays within 64 KB.
+// A tile of 2048 outputs plus a halo of w-1 in two padded LDS buffers stays
+// within 64 KB.
 uint32_t log_max_window() { return 4096; }
 
 int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
