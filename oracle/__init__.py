@@ -56,6 +56,9 @@ def _bind(lib):
     lib.oracle_base_code.restype = ctypes.c_int
     lib.oracle_kmers.argtypes = [u8p, u64, ctypes.c_uint32, ctypes.c_uint32, u64p]
     lib.oracle_kmers.restype = ll
+    lib.oracle_seed_table.argtypes = [u64p, u32p, u64, ctypes.c_uint32, ctypes.c_uint32, u64p,
+                                      u32p, u64p]
+    lib.oracle_seed_table.restype = ctypes.c_int
     for name in ("oracle_minimizers_naive", "oracle_minimizers_deque"):
         f = getattr(lib, name)
         f.argtypes = [u8p, u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
@@ -188,3 +191,22 @@ def minimizers_batch(seqs: np.ndarray, offsets: np.ndarray, k: int, w: int,
     if r < 0:
         raise ValueError("oracle batch minimizers rejected k=%d w=%d" % (k, w))
     return h[:r].copy(), p[:r].copy(), rd[:r].copy(), ro
+
+
+def seed_table(hash_, pos, bits: int, shift: int, lib=None):
+    """Seed pointer table (uint64[2^bits + 1]) and the positions and hashes
+    grouped by key = (hash >> shift) mod 2^bits, each group in input order."""
+    lib = lib or load()
+    h = np.ascontiguousarray(hash_, dtype=np.uint64)
+    p = np.ascontiguousarray(pos, dtype=np.uint32)
+    if h.size != p.size:
+        raise ValueError("hash and pos differ in length")
+    ptr = np.zeros((1 << bits) + 1, dtype=np.uint64)
+    po = np.zeros(max(p.size, 1), dtype=np.uint32)
+    ho = np.zeros(max(h.size, 1), dtype=np.uint64)
+    r = lib.oracle_seed_table(_ptr(h, ctypes.c_uint64), _ptr(p, ctypes.c_uint32), h.size, bits,
+                              shift, _ptr(ptr, ctypes.c_uint64), _ptr(po, ctypes.c_uint32),
+                              _ptr(ho, ctypes.c_uint64))
+    if r != 0:
+        raise ValueError("oracle seed table rejected bits=%d shift=%d" % (bits, shift))
+    return ptr, po[:p.size].copy(), ho[:h.size].copy()

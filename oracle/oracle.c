@@ -32,6 +32,11 @@
  *                             minimum the paper cites as the O(N) alternative
  *                             (Sec. 2.4, "Dequeue" in Sec. 4 / Fig. 3).
  *   oracle_minimizers_batch   the deque routine run once per read.
+ *   oracle_seed_table         Sec. 2.4 / Fig. 1: the seed pointer table and
+ *                             seed position table over the stored minimizers,
+ *                             keyed by key(h) = (h >> shift) mod 2^bits: a
+ *                             count per key, the prefix of the counts, and the
+ *                             entries placed key by key in their input order.
  *
  * Readings of points the paper leaves open (stated once here, used below):
  *   - identity of each operator pads nothing: the naive fold never needs it;
@@ -39,7 +44,13 @@
  *     2.4); any other byte is invalid and a k-mer covering it is invalid;
  *   - an invalid k-mer never wins a window; a window with no valid k-mer
  *     stores nothing; positions are 0-based k-mer start offsets;
- *   - n < w (or fewer than w k-mers) gives no output at all.
+ *   - n < w (or fewer than w k-mers) gives no output at all;
+ *   - the seed pointer table has 2^bits + 1 entries, ptr[j] = number of
+ *     entries with key < j, so the hits of key j are ptr[j] .. ptr[j+1] - 1.
+ *     The paper's table, whose entry for seed s ends the list of s (the
+ *     lookups of the seed before s and of s bound the hits of s), is
+ *     ptr[1 ..].  Within one key the entries keep their input (position)
+ *     order.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -345,4 +356,42 @@ long long oracle_minimizers_batch(const uint8_t *seqs, const uint64_t *offsets,
 /* Element-wise mix64 (inverse = 0) or its inverse (inverse = 1) over an array. */
 void oracle_mix64_array(const uint64_t *x, uint64_t n, int inverse, uint64_t *y) {
     for (uint64_t i = 0; i < n; ++i) y[i] = inverse ? oracle_mix64_inv(x[i]) : oracle_mix64(x[i]);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sec. 2.4 / Fig. 1: seed pointer table and seed position table.          */
+/* ---------------------------------------------------------------------- */
+
+/* Entries i = 0 .. count-1 are (hash[i], pos[i]) in input order; their key is
+ * (hash[i] >> shift) mod 2^bits.  Writes ptr[0 .. 2^bits] (ptr[j] = entries
+ * with key < j), and pos_out / hash_out (hash_out may be NULL) with the
+ * entries grouped by key, ascending, each group in input order.  Returns 0,
+ * or -1 for bits outside 1..32, shift + bits > 64, or a failed allocation. */
+int oracle_seed_table(const uint64_t *hash, const uint32_t *pos, uint64_t count,
+                      uint32_t bits, uint32_t shift, uint64_t *ptr, uint32_t *pos_out,
+                      uint64_t *hash_out) {
+    if (bits < 1 || bits > 32 || shift + bits > 64) return -1;
+    const uint64_t nkeys = 1ull << bits;
+    const uint64_t mask = nkeys - 1;
+    uint64_t *next = (uint64_t *)calloc(nkeys, sizeof(uint64_t));
+    if (!next) return -1;
+    /* counts per key */
+    for (uint64_t i = 0; i < count; ++i) next[(hash[i] >> shift) & mask] += 1;
+    /* ptr[j] = sum of the counts of keys below j */
+    uint64_t run = 0;
+    for (uint64_t j = 0; j < nkeys; ++j) {
+        ptr[j] = run;
+        run += next[j];
+        next[j] = ptr[j]; /* where the next entry of key j goes */
+    }
+    ptr[nkeys] = run;
+    /* entries in input order, each to the next free slot of its key */
+    for (uint64_t i = 0; i < count; ++i) {
+        const uint64_t j = (hash[i] >> shift) & mask;
+        pos_out[next[j]] = pos[i];
+        if (hash_out) hash_out[next[j]] = hash[i];
+        next[j] += 1;
+    }
+    free(next);
+    return 0;
 }

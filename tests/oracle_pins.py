@@ -443,9 +443,84 @@ def pin_batch(lib):
         assert int(ro[-1]) == h.size
 
 
+# ---------------------------------------------------------------- seed table pins
+def _seed_code(s):
+    return int("".join(str("ACGT".index(c)) for c in s), 4)
+
+
+def pin_fig1_seed_table(lib):
+    """Sec. 2.4 / Fig. 1 over the Fig. 2 minimizers: pointer and position tables."""
+    g = read_golden("fig1_seed_table.txt")
+    f2 = read_golden("fig2_worked_example.txt")
+    k = int(g["k"][0])
+    assert 4 ** k == int(g["seeds"][0])
+    h, p = oracle.minimizers(f2["sequence"][0], k, int(f2["w"][0]), canonical=False,
+                             hashed=False, lib=lib)
+    hits = g["hits"]
+    assert sorted(zip(h.tolist(), p.tolist())) == sorted(
+        (_seed_code(hits[i]), int(hits[i + 1])) for i in range(0, len(hits), 2))
+    ptr, po, ho = oracle.seed_table(h, p, 2 * k, 0, lib=lib)
+    # the paper's table is ptr[1:] (entry s closes the list of s)
+    paper = ptr[1:]
+    first = int(g["paper_pointer_nonzero_from"][0])
+    assert np.all(paper[:first] == 0) and paper[first] != 0
+    pp = g["paper_pointer"]
+    for i in range(0, len(pp), 2):
+        assert int(paper[_seed_code(pp[i])]) == int(pp[i + 1]), pp[i]
+    assert po.tolist() == [int(v) for v in g["position_table"]]
+    # hits of s lie between the lookups of the seed before s and of s
+    ct = _seed_code("CTT")
+    a, b = int(paper[ct - 1]), int(paper[ct])
+    assert po[a:b].tolist() == [2] and ho[a:b].tolist() == [ct]
+
+
+def _py_seed_table(h, p, bits, shift):
+    """Definition by Python's sorted(): entries ordered by (key, input index)."""
+    mask = (1 << bits) - 1
+    keys = [(int(x) >> shift) & mask for x in h]
+    order = sorted(range(len(keys)), key=lambda i: (keys[i], i))
+    ptr = [sum(1 for kk in keys if kk < j) for j in range((1 << bits) + 1)]
+    return ptr, [int(p[i]) for i in order], [int(h[i]) for i in order]
+
+
+def pin_seed_table_bruteforce(lib):
+    """Small random tables against the sorted() definition, every bits/shift
+    combination of a few widths, duplicate keys and empty input included."""
+    rng = np.random.default_rng(11)
+    for count in (0, 1, 2, 7, 40, 300):
+        for bits, shift in ((1, 0), (3, 0), (4, 60), (6, 5), (8, 56), (10, 30)):
+            h = rng.integers(0, 1 << 63, count, dtype=np.uint64) * np.uint64(2) + \
+                rng.integers(0, 2, count, dtype=np.uint64)
+            if count > 10:
+                h[: count // 3] = h[0]  # a heavy key
+            p = np.sort(rng.choice(10 * count + 1, count, replace=False)).astype(np.uint32)
+            ptr, po, ho = oracle.seed_table(h, p, bits, shift, lib=lib)
+            eptr, epo, eho = _py_seed_table(h, p, bits, shift)
+            assert ptr.tolist() == eptr, (count, bits, shift)
+            assert po.tolist() == epo and ho.tolist() == eho, (count, bits, shift)
+
+
+def pin_seed_table_invariants(lib):
+    """On minimizers of a random genome: the pointer table is monotone and ends
+    at the count; every group holds its own key only, in ascending position;
+    the table is a permutation of the input."""
+    rng = np.random.default_rng(12)
+    seq = _random_seq(rng, 20000, n_rate=0.01)
+    h, p = oracle.minimizers(seq, 15, 10, lib=lib)
+    for bits, shift in ((12, 52), (16, 0), (20, 44)):
+        ptr, po, ho = oracle.seed_table(h, p, bits, shift, lib=lib)
+        assert ptr[0] == 0 and int(ptr[-1]) == h.size and np.all(np.diff(ptr.astype(np.int64)) >= 0)
+        keys = (ho >> np.uint64(shift)) & np.uint64((1 << bits) - 1)
+        for j in rng.integers(0, 1 << bits, 200):
+            a, b = int(ptr[j]), int(ptr[j + 1])
+            assert np.all(keys[a:b] == j) and np.all(np.diff(po[a:b].astype(np.int64)) > 0)
+        assert sorted(zip(po.tolist(), ho.tolist())) == sorted(zip(p.tolist(), h.tolist()))
+
+
 ALL_PINS = [
     pin_sliding_bruteforce, pin_add_prefix_difference, pin_minmax_library,
     pin_minmax_composition, pin_affine_reductions, pin_paper_algorithms, pin_mix64,
     pin_kmers_strings, pin_kmer_strand_symmetry, pin_fig2_worked_example,
     pin_minimizers_bruteforce, pin_minimizers_invariants, pin_minimizer_density, pin_batch,
+    pin_fig1_seed_table, pin_seed_table_bruteforce, pin_seed_table_invariants,
 ]

@@ -30,6 +30,11 @@ MUTANTS = {
     "no_dedup": ("    if (same) return;\n", "\n"),
     "deque_window_off_by_one": ("uint64_t p = i + 1 - w;", "uint64_t p = i + 2 - w;"),
     "invalid_base_ignored": ("if (c < 0) return 0;", "if (c < 0) c = 0;"),
+    "seed_ptr_inclusive": ("        ptr[j] = run;\n        run += next[j];",
+                           "        run += next[j];\n        ptr[j] = run;"),
+    "seed_key_unshifted": ("next[(hash[i] >> shift) & mask] += 1;", "next[hash[i] & mask] += 1;"),
+    "seed_order_reversed": ("        pos_out[next[j]] = pos[i];",
+                            "        pos_out[ptr[j + 1] - 1 - (next[j] - ptr[j])] = pos[i];"),
 }
 
 
