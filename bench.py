@@ -156,6 +156,22 @@ def bench_sliding(torch, steps, warmup, quick):
     return out
 
 
+def bench_seed_table(torch, runner, count, steps, warmup):
+    """Seed pointer + position tables (Sec. 2.4, Fig. 1) over the step's
+    minimizers, keyed by the top 24 bits of the hash; algorithmic bytes =
+    12 B read + 12 B written per entry + the 4-byte pointer table."""
+    import paper_1811_10074_amd as sws
+    bits = 24
+    h, p = runner.hash[:count], runner.pos[:count]
+    st = sws.SeedTableRunner(count, bits)
+    ms, med, _ = time_launches(torch, lambda: st.launch(h, p, 64 - bits), steps, warmup)
+    algo = 24 * count + 4 * ((1 << bits) + 1)
+    return {"entries": count, "bits": bits, "ms": round(ms, 4), "median_ms": round(med, 4),
+            "Mentries/s": round(count / (ms / 1e3) / 1e6, 1),
+            "algorithmic_bytes": algo, "GB/s": round(algo / (ms / 1e3) / 1e9, 1),
+            "hbm_frac": round(algo / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 3)}
+
+
 def bench_batch(torch, quick):
     """Uneven reads in one launch (bucketed, tuned, graph) against one launch
     per read."""
@@ -389,6 +405,8 @@ def main():
         line["parity_prefix_2^20"] = bool(
             np.array_equal(runner.pos[: len(ep)].cpu().numpy().view(np.uint32), ep)
             and np.array_equal(runner.hash[: len(ep)].cpu().numpy().view(np.uint64), eh))
+    log("seed table over the timed minimizers")
+    line["seed_table"] = bench_seed_table(torch, runner, count, args.steps, args.warmup)
     del runner, seq, packed
     torch.cuda.empty_cache()
     log("sliding-sum extras")

@@ -219,6 +219,43 @@ int sws_minimizers_batch(const uint8_t *seqs, const uint64_t *d_offsets, uint32_
                          uint64_t ws_bytes, hipStream_t s);
 
 /* ------------------------------------------------------------------------ */
+/* Seed pointer table and seed position table, Sec. 2.4 and Fig. 1.           */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace bytes sws_seed_table needs for `count` entries. */
+int sws_seed_table_workspace(uint64_t count, uint32_t bits, uint64_t *bytes);
+
+/*
+ * Builds the seed table of Fig. 1 over count entries (hash[i], pos[i]), taken
+ * in input order (the output of sws_minimizers is in position order).  The
+ * table is keyed by key(h) = (h >> shift) mod 2^bits: with the k-mer value as
+ * the hash (SWS_HASH_IDENTITY), shift = 0 and bits = 2k it is the paper's
+ * table over all 4^k seeds in lexicographic order; with mix64 hashes, the top
+ * bits (shift = 64 - bits) give a hash-bucketed table.
+ *   hash, pos : device arrays of count entries (u64, u32); not modified.
+ *   count     : < 2^32.
+ *   bits      : 1 .. 30; shift + bits <= 64.
+ *   ptr       : device u32[2^bits + 1]: ptr[j] = number of entries with
+ *               key < j, so the hits of key j are pos_out[ptr[j] .. ptr[j+1]).
+ *               The paper's table, whose entry for a seed closes that seed's
+ *               list, is ptr + 1.
+ *   pos_out   : device u32[count]: the positions grouped by key, ascending,
+ *               each group in input order.
+ *   hash_out  : device u64[count] receiving the hashes in the same order, or
+ *               NULL.
+ *   workspace : ws_bytes bytes of device scratch, 16-byte aligned, at least
+ *               sws_seed_table_workspace(count, bits); contents on entry do
+ *               not matter.
+ * Outputs must not overlap the inputs or each other.
+ * Errors: SWS_ERR_INVALID (bits or shift out of range, null array with
+ * count > 0, null ptr), SWS_ERR_UNSUPPORTED (count >= 2^32),
+ * SWS_ERR_WORKSPACE, SWS_ERR_DEVICE.
+ */
+int sws_seed_table(const uint64_t *hash, const uint32_t *pos, uint64_t count, uint32_t bits,
+                   uint32_t shift, uint32_t *ptr, uint32_t *pos_out, uint64_t *hash_out,
+                   void *workspace, uint64_t ws_bytes, hipStream_t s);
+
+/* ------------------------------------------------------------------------ */
 /* Launch configuration (used by the autotuner).                              */
 /* ------------------------------------------------------------------------ */
 

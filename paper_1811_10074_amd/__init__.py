@@ -10,6 +10,7 @@ pointers and the current torch stream, and maps status codes to exceptions.
     minimizers(seq, k, w, ...)            Sec. 2.4 / Fig. 2 seeds: (hash, pos)
     minimizers_2bit(packed, invalid, n, k, w, ...)
     minimizers_batch(seqs, offsets, k, w, ...)
+    seed_table(hash, pos, bits, shift)    Sec. 2.4 / Fig. 1 pointer + position tables
 
 Device tensors hold unsigned data in signed torch dtypes (int32 for uint32,
 int64 for uint64); ``.view(numpy.uint32)`` etc. on the host restores the
@@ -22,7 +23,7 @@ import ctypes
 from . import _lib
 from ._lib import SwsError, check
 
-__all__ = ["sliding_sum", "pack2bit", "kmers", "minimizers", "minimizers_2bit",
+__all__ = ["sliding_sum", "pack2bit", "kmers", "minimizers", "minimizers_2bit", "seed_table",
            "minimizers_batch", "MinimizerRunner", "window_bound", "SwsError"]
 
 
@@ -182,3 +183,44 @@ def minimizers_2bit(packed, invalid, n: int, k: int, w: int, canonical: bool = T
 def minimizers_batch(seqs, offsets, k: int, w: int, canonical: bool = True, hashed: bool = True):
     from .batch import minimizers_batch as _mb
     return _mb(seqs, offsets, k, w, canonical=canonical, hashed=hashed)
+
+
+class SeedTableRunner:
+    """Preallocated outputs and workspace for seed tables of up to ``max_count``
+    entries keyed by ``bits`` bits (no allocation per call)."""
+
+    def __init__(self, max_count: int, bits: int, with_hash: bool = True, device="cuda"):
+        torch = _torch()
+        self.max_count, self.bits = max_count, bits
+        b = ctypes.c_uint64(0)
+        check(_lib.load().sws_seed_table_workspace(max_count, bits, ctypes.byref(b)),
+              "sws_seed_table_workspace")
+        self.ptr = torch.empty((1 << bits) + 1, dtype=torch.int32, device=device)
+        self.pos = torch.empty(max(max_count, 1), dtype=torch.int32, device=device)
+        self.hash = (torch.empty(max(max_count, 1), dtype=torch.int64, device=device)
+                     if with_hash else None)
+        self.workspace = torch.empty(max(int(b.value), 16), dtype=torch.uint8, device=device)
+
+    def launch(self, hash_, pos, shift: int):
+        """Enqueue on the current stream; results in self.ptr/pos/hash."""
+        count = pos.numel()
+        if hash_.numel() != count or count > self.max_count:
+            raise ValueError("hash and pos must have the same length, at most max_count")
+        st = _lib.load().sws_seed_table(_ptr(hash_), _ptr(pos), count, self.bits, shift,
+                                        _ptr(self.ptr), _ptr(self.pos), _ptr(self.hash),
+                                        _ptr(self.workspace), self.workspace.numel(), _stream())
+        check(st, "sws_seed_table")
+        self.count = count
+
+
+def seed_table(hash_, pos, bits: int, shift=None, with_hash: bool = True):
+    """Seed pointer table int32[2^bits + 1] (ptr[j] = entries with key < j) and
+    the positions (and hashes) grouped by key = (hash >> shift) mod 2^bits,
+    each group in input order.  shift defaults to 64 - bits (the top bits)."""
+    _need_cuda(hash_, "hash")
+    _need_cuda(pos, "pos")
+    shift = 64 - bits if shift is None else shift
+    r = SeedTableRunner(pos.numel(), bits, with_hash, device=pos.device)
+    r.launch(hash_, pos, shift)
+    n = pos.numel()
+    return r.ptr, r.pos[:n], (r.hash[:n] if with_hash else None)

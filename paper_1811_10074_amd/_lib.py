@@ -47,6 +47,9 @@ _SIGNATURES = {
                                      c_vp, c_u64, c_vp, c_vp, c_u64, c_vp]),
     "sws_set_minimizer_block": (c_int, [c_u32, c_u32]),
     "sws_set_sliding_waves": (c_int, [c_u64]),
+    "sws_seed_table_workspace": (c_int, [c_u64, c_u32, c_vp]),
+    "sws_seed_table": (c_int, [c_vp, c_vp, c_u64, c_u32, c_u32, c_vp, c_vp, c_vp, c_vp, c_u64,
+                               c_vp]),
 }
 
 

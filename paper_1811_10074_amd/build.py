@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsws.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["sliding.hip", "genome.hip", "batch.hip", "api.cpp"]
+SOURCES = ["sliding.hip", "genome.hip", "seedtable.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for every HIP translation unit.

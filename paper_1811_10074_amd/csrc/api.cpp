@@ -260,6 +260,29 @@ int sws_minimizers_batch(const uint8_t* seqs, const uint64_t* d_offsets, uint32_
                ? SWS_OK : SWS_ERR_DEVICE;
 }
 
+int sws_seed_table_workspace(uint64_t count, uint32_t bits, uint64_t* bytes) {
+    if (bytes == nullptr || bits < 1 || bits > 30) return SWS_ERR_INVALID;
+    if (count > 0xFFFFFFFFull) return SWS_ERR_UNSUPPORTED;
+    *bytes = sws::seed_table_workspace_bytes(count);
+    return SWS_OK;
+}
+
+int sws_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count, uint32_t bits,
+                   uint32_t shift, uint32_t* ptr, uint32_t* pos_out, uint64_t* hash_out,
+                   void* workspace, uint64_t ws_bytes, hipStream_t s) {
+    if (bits < 1 || bits > 30 || shift > 64u - bits || ptr == nullptr) return SWS_ERR_INVALID;
+    if (count > 0xFFFFFFFFull) return SWS_ERR_UNSUPPORTED;
+    if (count > 0 && (hash == nullptr || pos == nullptr || pos_out == nullptr))
+        return SWS_ERR_INVALID;
+    if (workspace == nullptr || ws_bytes < sws::seed_table_workspace_bytes(count) ||
+        ((uintptr_t)workspace & 15u))
+        return SWS_ERR_WORKSPACE;
+    return sws::launch_seed_table(hash, pos, count, bits, shift, ptr, pos_out, hash_out,
+                                  workspace, s) == 0
+               ? SWS_OK
+               : SWS_ERR_DEVICE;
+}
+
 int sws_set_sliding_waves(uint64_t waves) {
     if (waves > (1ull << 24)) return SWS_ERR_INVALID;
     g_sliding_waves = waves;

@@ -74,6 +74,12 @@ int launch_kmers(const GenomeInput& in, uint32_t k, uint32_t flags, uint64_t* ou
 uint32_t minimizer_tile_windows(uint32_t nt, uint32_t w);
 uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t w);
 uint64_t minimizer_workspace_bytes(uint64_t ntiles);
+
+// Seed pointer/position tables (seedtable.hip).
+uint64_t seed_table_workspace_bytes(uint64_t count);
+int launch_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count, uint32_t bits,
+                      uint32_t shift, uint32_t* ptr, uint32_t* pos_out, uint64_t* hash_out,
+                      void* workspace, hipStream_t s);
 int launch_minimizers(const GenomeInput& in, MinimizerArgs a, uint32_t nt, void* workspace,
                       hipStream_t s);
 

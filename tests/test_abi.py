@@ -82,4 +82,22 @@ def test_minimizer_validation(lib):
     assert lib.sws_set_minimizer_block(0, 100) == _lib.SWS_ERR_INVALID
     assert lib.sws_set_minimizer_block(3, 256) == _lib.SWS_ERR_INVALID
     assert lib.sws_set_sliding_waves((1 << 24) + 1) == _lib.SWS_ERR_INVALID
+    # seed table: argument checks happen before anything is enqueued
+    b = ctypes.c_uint64(0)
+    assert lib.sws_seed_table_workspace(1000, 0, ctypes.byref(b)) == _lib.SWS_ERR_INVALID
+    assert lib.sws_seed_table_workspace(1000, 31, ctypes.byref(b)) == _lib.SWS_ERR_INVALID
+    assert lib.sws_seed_table_workspace(1 << 32, 16, ctypes.byref(b)) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_seed_table_workspace(1000, 16, ctypes.byref(b)) == _lib.SWS_OK and b.value > 0
+    need = b.value
+    st = lambda cnt, bits, shift, ws, wsb, h=FAKE, po=FAKE, ptr=FAKE: lib.sws_seed_table(
+        h, FAKE, cnt, bits, shift, ptr, po, NULL, ws, wsb, s)
+    assert st(1000, 16, 49, FAKE, need) == _lib.SWS_ERR_INVALID          # shift + bits > 64
+    assert st(1000, 0, 0, FAKE, need) == _lib.SWS_ERR_INVALID
+    assert st(1000, 16, 48, FAKE, need, ptr=NULL) == _lib.SWS_ERR_INVALID
+    assert st(1000, 16, 48, FAKE, need, h=NULL) == _lib.SWS_ERR_INVALID
+    assert st(1000, 16, 48, FAKE, need, po=NULL) == _lib.SWS_ERR_INVALID
+    assert st(1 << 32, 16, 48, FAKE, need) == _lib.SWS_ERR_UNSUPPORTED
+    assert st(1000, 16, 48, NULL, need) == _lib.SWS_ERR_WORKSPACE
+    assert st(1000, 16, 48, FAKE, need - 1) == _lib.SWS_ERR_WORKSPACE
+    assert st(1000, 16, 48, ctypes.c_void_p(0x10008), need) == _lib.SWS_ERR_WORKSPACE
     assert lib.sws_set_sliding_waves(0) == _lib.SWS_OK
