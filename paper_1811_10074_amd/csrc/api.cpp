@@ -263,7 +263,7 @@ int sws_minimizers_batch(const uint8_t* seqs, const uint64_t* d_offsets, uint32_
 int sws_seed_table_workspace(uint64_t count, uint32_t bits, uint64_t* bytes) {
     if (bytes == nullptr || bits < 1 || bits > 30) return SWS_ERR_INVALID;
     if (count > 0xFFFFFFFFull) return SWS_ERR_UNSUPPORTED;
-    *bytes = sws::seed_table_workspace_bytes(count);
+    *bytes = sws::seed_table_workspace_bytes(count, bits);
     return SWS_OK;
 }
 
@@ -274,7 +274,7 @@ int sws_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count, ui
     if (count > 0xFFFFFFFFull) return SWS_ERR_UNSUPPORTED;
     if (count > 0 && (hash == nullptr || pos == nullptr || pos_out == nullptr))
         return SWS_ERR_INVALID;
-    if (workspace == nullptr || ws_bytes < sws::seed_table_workspace_bytes(count) ||
+    if (workspace == nullptr || ws_bytes < sws::seed_table_workspace_bytes(count, bits) ||
         ((uintptr_t)workspace & 15u))
         return SWS_ERR_WORKSPACE;
     return sws::launch_seed_table(hash, pos, count, bits, shift, ptr, pos_out, hash_out,

@@ -76,7 +76,7 @@ uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t w);
 uint64_t minimizer_workspace_bytes(uint64_t ntiles);
 
 // Seed pointer/position tables (seedtable.hip).
-uint64_t seed_table_workspace_bytes(uint64_t count);
+uint64_t seed_table_workspace_bytes(uint64_t count, uint32_t bits);
 int launch_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count, uint32_t bits,
                       uint32_t shift, uint32_t* ptr, uint32_t* pos_out, uint64_t* hash_out,
                       void* workspace, hipStream_t s);
