@@ -59,12 +59,15 @@ typedef enum {
 
 /* How the sliding sum is computed.  All paths give identical bits. */
 typedef enum {
-    SWS_PATH_AUTO = 0,    /* the library picks per (op, w)                                              */
+    SWS_PATH_AUTO = 0,    /* the library picks per (op, w): PREFIX for ADD with w > 512, else GENERIC   */
     SWS_PATH_GENERIC = 1, /* block prefix/suffix scans: Alg. 2 of Sec. 3.1 with block length w, any
                              associative op, O(1) operator applications per output                    */
-    SWS_PATH_LOG = 2      /* doubling of overlapping windows, O(log w) per output; only for MIN and MAX,
+    SWS_PATH_LOG = 2,     /* doubling of overlapping windows, O(log w) per output; only for MIN and MAX,
                              whose idempotence lets two overlapping halves cover a window (Sec. 3.1,
                              the commutative case); SWS_ERR_UNSUPPORTED for ADD and AFFINE            */
+    SWS_PATH_PREFIX = 3   /* difference of running prefixes, y_i = P_{i+w-1} - P_{i-1} (the invertible
+                             case named in the conclusion): one scan, cost independent of w; only for
+                             ADD; SWS_ERR_UNSUPPORTED for the others                                  */
 } sws_path;
 
 /* k-mer / minimizer flags (bitwise or). */
@@ -110,7 +113,8 @@ enum {
 int sws_sliding_sum(int op, uint64_t w, const void *x, uint64_t n, void *y, hipStream_t s);
 
 /* As sws_sliding_sum with an explicit path (sws_path).  SWS_PATH_LOG with ADD
- * or AFFINE returns SWS_ERR_UNSUPPORTED. */
+ * or AFFINE, and SWS_PATH_PREFIX with anything but ADD, return
+ * SWS_ERR_UNSUPPORTED. */
 int sws_sliding_sum_ex(int op, uint64_t w, const void *x, uint64_t n, void *y, int path,
                        hipStream_t s);
 

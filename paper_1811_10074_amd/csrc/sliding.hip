@@ -181,12 +181,17 @@ __host__ __device__ constexpr uint32_t ring_rows(uint32_t w) {
     return (128u + (R + w - 2u) / R + 3u) & ~3u;
 }
 
-template <class Op, int R, int WAVES>
+// PFX: the prefix-difference form for an invertible operator (+ mod 2^32):
+// y_i = P_{i+w-1} - P_{i-1} with P a running prefix local to the wave (an
+// offset common to both terms cancels).  The ring then holds P, the suffix
+// registers hold the exclusive prefix, and the segment masks are unused.
+template <class Op, int R, int WAVES, bool PFX = false>
 __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
     const typename Op::T* __restrict__ x, uint64_t n, uint32_t w, typename Op::T* __restrict__ y,
     uint64_t count, uint64_t total_slabs, uint64_t slabs_per_wave, int vec, uint32_t rows) {
     using T = typename Op::T;
     using IO = SlabIO<T, R>;
+    static_assert(!PFX || sizeof(T) == 4, "the prefix-difference form is for + on u32");
     constexpr uint32_t S = kWave * R;
     constexpr uint32_t RS = R + 1;              // ring row stride (elements)
     constexpr uint32_t REGION = kWave * RS;     // elements per slab region
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
     if (s0 >= total_slabs) return;
     const uint64_t s1 = s0 + slabs_per_wave < total_slabs ? s0 + slabs_per_wave : total_slabs;
 
-    const uint32_t span = (w + R - 1) / R;
+    const uint32_t span = PFX ? (uint32_t)kWave : (w + R - 1) / R;
     const uint32_t head_chunks = (uint32_t)(((w - 1u) * sizeof(T) + 15u) / 16u);  // first w - 1 elements
     const uint32_t mirror = (R + w - 2u) / R;  // rows of region 0 repeated from row 128
     const uint32_t lane_row = (uint32_t)lane * RS;
@@ -225,15 +230,20 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
         IO::to_run(stage_of(1), lane, raw, v);
         uint32_t m0 = mA + lane_mod;
         m0 = m0 >= w ? m0 - w : m0;
-        headsA = lane_heads<R>(m0, w, pat);
+        headsA = PFX ? (HeadMask<R>)0 : lane_heads<R>(m0, w, pat);
 #pragma unroll
         for (int e = 0; e < R; ++e) sfA[e] = v[e];
         slab_prefix<Op, R>(v, headsA, span, lane, ident);
 #pragma unroll
         for (int e = 0; e < R; ++e) ring[lane_row + e] = v[e];
         carryA = lane_value(v[R - 1], kWave - 1);
-        slab_suffix<Op, R>(sfA, headsA, span, lane);
-        heads_to_identity<R>(sfA, headsA, ident);
+        if constexpr (PFX) {
+#pragma unroll
+            for (int e = 0; e < R; ++e) sfA[e] = v[e] - sfA[e];  // exclusive prefix
+        } else {
+            slab_suffix<Op, R>(sfA, headsA, span, lane);
+            heads_to_identity<R>(sfA, headsA, ident);
+        }
     }
     // slab B; when it is the next wave's first slab, only its first w - 1
     // elements enter this wave's outputs
@@ -268,7 +278,7 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
                                         lane, v16, ident, raw);
             uint32_t m0 = mB + lane_mod;
             m0 = m0 >= w ? m0 - w : m0;
-            headsB = lane_heads<R>(m0, w, pat);
+            headsB = PFX ? (HeadMask<R>)0 : lane_heads<R>(m0, w, pat);
 #pragma unroll
             for (int e = 0; e < R; ++e) sfB[e] = v[e];
             slab_prefix<Op, R>(v, headsB, span, lane, carryA);
@@ -280,12 +290,17 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
                 for (int e = 0; e < R; ++e) rowB[2 * REGION + e] = v[e];
             }
             carryA = lane_value(v[R - 1], kWave - 1);
-            slab_suffix<Op, R>(sfB, headsB, span, lane);
-            heads_to_identity<R>(sfB, headsB, ident);
+            if constexpr (PFX) {
+#pragma unroll
+                for (int e = 0; e < R; ++e) sfB[e] = v[e] - sfB[e];  // exclusive prefix
+            } else {
+                slab_suffix<Op, R>(sfB, headsB, span, lane);
+                heads_to_identity<R>(sfB, headsB, ident);
+            }
         }
         // the last segment of A continues into B: append B's leading suffix
         // (B's first element is not a head here, so sfB[0] in lane 0 is real)
-        {
+        if constexpr (!PFX) {
             const T c = lane_value(sfB[0], 0);
             const uint32_t last = (mA + S - 1u) % w;
             if (last != w - 1u) {
@@ -306,7 +321,8 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
 #pragma unroll
             for (int e = 0; e < R; ++e) {
                 const uint32_t q = w - 1u + (uint32_t)e;
-                out[e] = Op::combine(sfA[e], rowA[q + q / R]);
+                if constexpr (PFX) out[e] = rowA[q + q / R] - sfA[e];  // P_{i+w-1} - P_{i-1}
+                else out[e] = Op::combine(sfA[e], rowA[q + q / R]);
             }
             IO::template store<CHECK>(y, count, baseA, lane, v16, stage_of(half), out);
         }
@@ -456,7 +472,7 @@ __global__ __launch_bounds__(NT) void sliding_log_kernel(const uint32_t* __restr
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-template <class Op, int R, int WAVES>
+template <class Op, int R, int WAVES, bool PFX = false>
 static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
                           uint64_t target_waves, hipStream_t s) {
     using T = typename Op::T;
@@ -469,7 +485,7 @@ static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64
     const int vec = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0 ? 1 : 0;
     const uint32_t rows = ring_rows<R>(w);
     const size_t lds = (size_t)WAVES * rows * (R + 1) * sizeof(T);
-    hipLaunchKernelGGL((sliding_generic_kernel<Op, R, WAVES>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((sliding_generic_kernel<Op, R, WAVES, PFX>), dim3((unsigned)blocks),
                        dim3(WAVES * kWave), lds, s, static_cast<const T*>(x), n, w,
                        static_cast<T*>(y), count, total_slabs, spw, vec, rows);
     return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -516,6 +532,14 @@ int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* 
         return launch_generic<OpAffine, 8, 2>(x, n, w, y, count, tw, s);
     default: return -2;
     }
+}
+
+// The prefix-difference form, + only (the one invertible operator here).
+int launch_sliding_prefix(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
+                          uint64_t tw, hipStream_t s) {
+    if (op != kOpAdd) return -2;
+    return w > (uint32_t)(kWave * 16) ? launch_generic<OpAdd, 32, 1, true>(x, n, w, y, count, tw, s)
+                                      : launch_generic<OpAdd, 16, 2, true>(x, n, w, y, count, tw, s);
 }
 
 int launch_sliding_log(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,

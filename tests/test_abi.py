@@ -82,6 +82,10 @@ def test_minimizer_validation(lib):
     assert lib.sws_set_minimizer_block(0, 100) == _lib.SWS_ERR_INVALID
     assert lib.sws_set_minimizer_block(3, 256) == _lib.SWS_ERR_INVALID
     assert lib.sws_set_sliding_waves((1 << 24) + 1) == _lib.SWS_ERR_INVALID
+    # the prefix-difference path exists for + only
+    for op in (1, 2, 3):
+        assert lib.sws_sliding_sum_ex(op, 4, FAKE, 100, FAKE, 3, s) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_sliding_sum_ex(0, 4, FAKE, 100, FAKE, 4, s) == _lib.SWS_ERR_INVALID
     # seed table: argument checks happen before anything is enqueued
     b = ctypes.c_uint64(0)
     assert lib.sws_seed_table_workspace(1000, 0, ctypes.byref(b)) == _lib.SWS_ERR_INVALID

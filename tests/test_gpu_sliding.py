@@ -54,6 +54,14 @@ def test_window_sweep_generic(op):
         check(torch, op, w, x, "generic")
 
 
+def test_window_sweep_prefix():
+    """The prefix-difference path (+ only) over the generic sweep's windows."""
+    torch = torch_cuda()
+    for w in WINDOWS:
+        n = 3 * S16 * 2 + 37 + w
+        check(torch, "add", w, inputs.uniform_u32(n, 60 + w), "prefix")
+
+
 @pytest.mark.parametrize("op", ["min", "max"])
 def test_window_sweep_log(op):
     torch = torch_cuda()
@@ -153,7 +161,8 @@ def test_config3_full_size_sampled(op):
     rng = np.random.default_rng(99)
     x = inputs.affine_pairs(n, seed=2, odd=True) if op == "affine" else inputs.uniform_u32(n, seed=2)
     t = dev(x, torch)
-    paths = ["generic", "log"] if op in ("min", "max") else ["generic"]
+    paths = {"min": ["generic", "log"], "max": ["generic", "log"], "add": ["generic", "prefix"],
+             "affine": ["generic"]}[op]
     for w in (4, 16, 64, 256, 1024):
         for path in paths:
             y = sws.sliding_sum(op, w, t, path=path)
@@ -203,6 +212,8 @@ def test_long_streams_per_wave(few_waves, waves, op):
             x = inputs.affine_pairs(n, seed + n, odd=True) if op == "affine" else \
                 inputs.uniform_u32(n, seed + n)
             check(torch, op, w, x, "generic")
+            if op == "add":
+                check(torch, op, w, x, "prefix")
 
 
 @pytest.mark.parametrize("waves", [1, 3])
