@@ -135,7 +135,9 @@ def bench_sliding(torch, steps, warmup, quick):
             continue
         src = xa if op == "affine" else x
         esz = 8 if op == "affine" else 4
-        for path in (("generic", "log") if op in ("min", "max") else ("generic",)):
+        paths = {"min": ("generic", "log"), "max": ("generic", "log"), "add": ("generic", "prefix"),
+                 "affine": ("generic",)}[op]
+        for path in paths:
             for w in ((16, 1024) if quick else (4, 16, 64, 256, 1024)):
                 cnt = n - w + 1
                 y = torch.empty((cnt, 2) if op == "affine" else (cnt,), dtype=torch.int32, device="cuda")
