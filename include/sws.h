@@ -65,9 +65,12 @@ typedef enum {
     SWS_PATH_LOG = 2,     /* doubling of overlapping windows, O(log w) per output; only for MIN and MAX,
                              whose idempotence lets two overlapping halves cover a window (Sec. 3.1,
                              the commutative case); SWS_ERR_UNSUPPORTED for ADD and AFFINE            */
-    SWS_PATH_PREFIX = 3   /* difference of running prefixes, y_i = P_{i+w-1} - P_{i-1} (the invertible
+    SWS_PATH_PREFIX = 3,  /* difference of running prefixes, y_i = P_{i+w-1} - P_{i-1} (the invertible
                              case named in the conclusion): one scan, cost independent of w; only for
                              ADD; SWS_ERR_UNSUPPORTED for the others                                  */
+    SWS_PATH_SCALAR = 4   /* Alg. 1 of Sec. 3.1 (scalar input): one wavefront keeps the w-1 running
+                             suffix sums in its lanes and takes the input one element at a time; any
+                             op, w <= 64 (SWS_ERR_UNSUPPORTED above)                                  */
 } sws_path;
 
 /* k-mer / minimizer flags (bitwise or). */

@@ -21,7 +21,7 @@ SWS_ERR_DEVICE = -4
 SWS_ERR_UNSUPPORTED = -5
 
 OPS = {"add": 0, "min": 1, "max": 2, "affine": 3}
-PATHS = {"auto": 0, "generic": 1, "log": 2, "prefix": 3}
+PATHS = {"auto": 0, "generic": 1, "log": 2, "prefix": 3, "scalar": 4}
 KMER_FORWARD = 1
 HASH_IDENTITY = 2
 

@@ -102,7 +102,7 @@ const char* sws_status_str(int status) {
 int sws_sliding_sum_ex(int op, uint64_t w, const void* x, uint64_t n, void* y, int path,
                        hipStream_t s) {
     if (op < SWS_OP_ADD_U32 || op > SWS_OP_AFFINE_U32) return SWS_ERR_INVALID;
-    if (path < SWS_PATH_AUTO || path > SWS_PATH_PREFIX) return SWS_ERR_INVALID;
+    if (path < SWS_PATH_AUTO || path > SWS_PATH_SCALAR) return SWS_ERR_INVALID;
     if (w == 0) return SWS_ERR_INVALID;
     const bool idem = op == SWS_OP_MIN_U32 || op == SWS_OP_MAX_U32;
     if (path == SWS_PATH_LOG && !idem) return SWS_ERR_UNSUPPORTED;
@@ -122,6 +122,12 @@ int sws_sliding_sum_ex(int op, uint64_t w, const void* x, uint64_t n, void* y, i
         if (w > sws::log_max_window()) return SWS_ERR_UNSUPPORTED;
         return sws::launch_sliding_log(op, x, n, (uint32_t)w, y, count, s) == 0 ? SWS_OK
                                                                                : SWS_ERR_DEVICE;
+    }
+    if (use == SWS_PATH_SCALAR) {
+        if (w > sws::scalar_max_window()) return SWS_ERR_UNSUPPORTED;
+        return sws::launch_sliding_scalar(op, x, n, (uint32_t)w, y, count, s) == 0
+                   ? SWS_OK
+                   : SWS_ERR_DEVICE;
     }
     if (w > sws::generic_max_window()) return SWS_ERR_UNSUPPORTED;
     const uint64_t waves = g_sliding_waves ? g_sliding_waves : kDefaultSlidingWaves;

@@ -44,6 +44,7 @@
 #include "sws_scan.hpp"
 
 #include <type_traits>
+#include <utility>
 
 namespace sws {
 
@@ -466,6 +467,141 @@ __global__ __launch_bounds__(NT) void sliding_log_kernel(const uint32_t* __restr
             for (int k = 0; k < 4; ++k)
                 if (g + k < count) y[g + k] = r[k];
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Scalar-input path (Alg. 1 of Sec. 3.1), w <= 64, any associative operator.
+//
+// A vector of G lanes (G = 16 for w <= 16, four such vectors per wavefront,
+// one per 16-lane row; else G = 64) streams a run of outputs.  Lane l < w
+// holds Y[l]; before input x_i arrives, Y[l] = x_{i-w+1+l} (+) ... (+)
+// x_{i-1} (lanes l >= w - 1 hold the identity).  Each input is broadcast to
+// lanes 0 .. w-1 and added on the right (Y stays the left operand), lane 0
+// then holds the window x_{i-w+1} .. x_i, and Y moves down one lane.  The first
+// w - 1 inputs of the run only fill Y, which gives exactly the initial suffix
+// sums of Alg. 1.  Inputs come in G at a time (one per lane); the outputs of
+// G steps are collected by shifting them in at lane 0 and leave as one store.
+// The moves are DPP lane shifts (row-wise for G = 16, wave-wide for G = 64).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kScalarRun = 4096;  // outputs per vector
+
+template <int G>
+struct ScalarLanes;
+template <>
+struct ScalarLanes<16> {  // 16-lane rows
+    static constexpr int kDown = 0x101, kUp = 0x111;  // row_shl:1, row_shr:1
+    template <int K>
+    static __device__ __forceinline__ uint32_t bcast(uint32_t v) {  // row_newbcast:K
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + K, 0xF, 0xF, false);
+    }
+};
+template <>
+struct ScalarLanes<64> {  // the whole wavefront
+    static constexpr int kDown = 0x130, kUp = 0x138;  // wave_shl:1, wave_shr:1
+    template <int K>
+    static __device__ __forceinline__ uint32_t bcast(uint32_t v) {
+        return (uint32_t)__builtin_amdgcn_readlane((int)v, K);
+    }
+};
+
+// lane l takes lane l + 1 (DOWN) or l - 1 (UP) of its vector; the lane with
+// no source keeps `keep`
+template <int CTRL>
+__device__ __forceinline__ uint32_t lane_move(uint32_t v, uint32_t keep) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)keep, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint2 lane_move(uint2 v, uint2 keep) {
+    return make_uint2(lane_move<CTRL>(v.x, keep.x), lane_move<CTRL>(v.y, keep.y));
+}
+template <class L, int K>
+__device__ __forceinline__ uint32_t lane_bcast(uint32_t v) { return L::template bcast<K>(v); }
+template <class L, int K>
+__device__ __forceinline__ uint2 lane_bcast(uint2 v) {
+    return make_uint2(L::template bcast<K>(v.x), L::template bcast<K>(v.y));
+}
+
+template <class Op, int G, int K>
+__device__ __forceinline__ void scalar_step(typename Op::T& Y, typename Op::T& ov,
+                                            typename Op::T xv, bool in_window,
+                                            typename Op::T ident) {
+    using L = ScalarLanes<G>;
+    const typename Op::T xi = lane_bcast<L, K>(xv);
+    Y = in_window ? Op::combine(Y, xi) : ident;
+    ov = lane_move<L::kUp>(ov, Y);     // lane 0 takes this step's window
+    Y = lane_move<L::kDown>(Y, ident);
+}
+
+template <class Op, int G, int... K>
+__device__ __forceinline__ void scalar_block(typename Op::T& Y, typename Op::T& ov,
+                                             typename Op::T xv, bool in_window,
+                                             typename Op::T ident,
+                                             std::integer_sequence<int, K...>) {
+    (scalar_step<Op, G, K>(Y, ov, xv, in_window, ident), ...);
+}
+
+template <class Op, int G>
+__global__ __launch_bounds__(256) void sliding_scalar_kernel(const typename Op::T* __restrict__ x,
+                                                             uint64_t n, uint32_t w,
+                                                             typename Op::T* __restrict__ y,
+                                                             uint64_t count) {
+    using T = typename Op::T;
+    constexpr int NV = kWave / G;  // vectors per wavefront
+    const int lane = lane_id();
+    const int j = lane % G;        // lane within the vector
+    const uint64_t v = ((uint64_t)blockIdx.x * 4 + (uint64_t)wave_id()) * NV + (uint64_t)(lane / G);
+    const uint64_t o0 = v * kScalarRun;
+    // every vector of a wavefront takes the same number of steps; a vector
+    // past the end computes nothing that is stored
+    const uint64_t o0w = ((uint64_t)blockIdx.x * 4 + (uint64_t)wave_id()) * NV * kScalarRun;
+    if (o0w >= count) return;
+    const uint64_t o1 = o0 + kScalarRun < count ? o0 + kScalarRun : (o0 < count ? count : o0);
+    const uint64_t iend = o1 + w - 1 <= n ? o1 + w - 1 : n;  // this vector's inputs o0 .. iend - 1
+    const uint64_t steps = kScalarRun + w - 1;
+    const T ident = Op::identity();
+    const bool in_window = (uint32_t)j < w;
+    T Y = ident, ov = ident;
+    for (uint64_t t = 0; t < steps; t += G) {
+        const uint64_t gi = o0 + t + (uint64_t)j;
+        const T xv = gi < iend ? x[gi] : ident;
+        scalar_block<Op, G>(Y, ov, xv, in_window, ident, std::make_integer_sequence<int, G>());
+        // lane j holds the window that ended at input o0 + t + G - 1 - j
+        const uint64_t last = o0 + t + (uint64_t)(G - 1 - j);  // its last input
+        if (last + 1 >= o0 + w) {
+            const uint64_t oi = last + 1 - w;                   // its output index
+            if (oi < o1) y[oi] = ov;
+        }
+    }
+}
+
+template <class Op>
+static int launch_scalar(const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
+                         hipStream_t s) {
+    using T = typename Op::T;
+    const uint64_t vecs = (count + kScalarRun - 1) / kScalarRun;
+    if (w <= 16u) {
+        const uint64_t blocks = (vecs + 15) / 16;  // 4 vectors per wave, 4 waves per block
+        hipLaunchKernelGGL((sliding_scalar_kernel<Op, 16>), dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<const T*>(x), n, w, static_cast<T*>(y), count);
+    } else {
+        const uint64_t blocks = (vecs + 3) / 4;
+        hipLaunchKernelGGL((sliding_scalar_kernel<Op, 64>), dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<const T*>(x), n, w, static_cast<T*>(y), count);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+uint32_t scalar_max_window() { return kWave; }
+
+int launch_sliding_scalar(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
+                          hipStream_t s) {
+    switch (op) {
+    case kOpAdd: return launch_scalar<OpAdd>(x, n, w, y, count, s);
+    case kOpMin: return launch_scalar<OpMin>(x, n, w, y, count, s);
+    case kOpMax: return launch_scalar<OpMax>(x, n, w, y, count, s);
+    case kOpAffine: return launch_scalar<OpAffine>(x, n, w, y, count, s);
+    default: return -2;
     }
 }
 

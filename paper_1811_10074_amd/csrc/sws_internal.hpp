@@ -16,6 +16,9 @@ uint32_t log_max_window();
 // ceil(slabs / target_waves) consecutive slabs.
 int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
                            uint64_t target_waves, hipStream_t s);
+uint32_t scalar_max_window();
+int launch_sliding_scalar(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
+                          hipStream_t s);
 int launch_sliding_prefix(int op, const void* x, uint64_t n, uint32_t w, void* y,
                           uint64_t count, uint64_t target_waves, hipStream_t s);
 int launch_sliding_log(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,

@@ -85,7 +85,8 @@ def test_minimizer_validation(lib):
     # the prefix-difference path exists for + only
     for op in (1, 2, 3):
         assert lib.sws_sliding_sum_ex(op, 4, FAKE, 100, FAKE, 3, s) == _lib.SWS_ERR_UNSUPPORTED
-    assert lib.sws_sliding_sum_ex(0, 4, FAKE, 100, FAKE, 4, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_sliding_sum_ex(0, 65, FAKE, 100, FAKE, 4, s) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_sliding_sum_ex(0, 4, FAKE, 100, FAKE, 5, s) == _lib.SWS_ERR_INVALID
     # seed table: argument checks happen before anything is enqueued
     b = ctypes.c_uint64(0)
     assert lib.sws_seed_table_workspace(1000, 0, ctypes.byref(b)) == _lib.SWS_ERR_INVALID

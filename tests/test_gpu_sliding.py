@@ -62,6 +62,19 @@ def test_window_sweep_prefix():
         check(torch, "add", w, inputs.uniform_u32(n, 60 + w), "prefix")
 
 
+@pytest.mark.parametrize("op", ["add", "min", "max", "affine"])
+def test_window_sweep_scalar(op):
+    """Alg. 1 (scalar input) for every op and w up to 64, over several
+    4096-output wavefront runs with a ragged tail."""
+    torch = torch_cuda()
+    seed = {"add": 70, "min": 71, "max": 72, "affine": 73}[op]
+    for w in [1, 2, 3, 5, 10, 16, 17, 31, 32, 33, 63, 64]:
+        for n in (w, w + 1, 64 + w, 3 * 4096 + 77 + w):
+            x = inputs.affine_pairs(n, seed + w, odd=True) if op == "affine" else \
+                inputs.uniform_u32(n, seed + w)
+            check(torch, op, w, x, "scalar")
+
+
 @pytest.mark.parametrize("op", ["min", "max"])
 def test_window_sweep_log(op):
     torch = torch_cuda()
