@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 OPS = {"add": 0, "min": 1, "max": 2, "affine": 3}
 FORWARD = 1   # forward k-mer instead of canonical
 IDENTITY = 2  # k-mer value instead of its hash
+SPLIT = 4     # invalid bases split the sequence into segments
 
 _lock = threading.Lock()
 _lib = None
@@ -128,8 +129,8 @@ def mix64(x, inverse: bool = False, lib=None):
     return y
 
 
-def flags_of(canonical: bool = True, hashed: bool = True) -> int:
-    return (0 if canonical else FORWARD) | (0 if hashed else IDENTITY)
+def flags_of(canonical: bool = True, hashed: bool = True, split: bool = False) -> int:
+    return (0 if canonical else FORWARD) | (0 if hashed else IDENTITY) | (SPLIT if split else 0)
 
 
 def kmers(seq, k: int, canonical: bool = True, hashed: bool = True, lib=None) -> np.ndarray:
@@ -150,8 +151,9 @@ def window_bound(n: int, k: int, w: int) -> int:
 
 
 def minimizers(seq, k: int, w: int, canonical: bool = True, hashed: bool = True,
-               method: str = "deque", lib=None):
-    """Deduplicated (hash uint64, pos uint32) minimizers of one sequence."""
+               method: str = "deque", lib=None, split: bool = False):
+    """Deduplicated (hash uint64, pos uint32) minimizers of one sequence
+    (split: invalid bases cut it into segments, see oracle.c)."""
     lib = lib or load()
     s = _as_bytes(seq)
     n = s.size
@@ -159,7 +161,7 @@ def minimizers(seq, k: int, w: int, canonical: bool = True, hashed: bool = True,
     h = np.zeros(max(cap, 1), dtype=np.uint64)
     p = np.zeros(max(cap, 1), dtype=np.uint32)
     f = lib.oracle_minimizers_naive if method == "naive" else lib.oracle_minimizers_deque
-    r = f(_ptr(s, ctypes.c_uint8), n, k, w, flags_of(canonical, hashed),
+    r = f(_ptr(s, ctypes.c_uint8), n, k, w, flags_of(canonical, hashed, split),
           _ptr(h, ctypes.c_uint64), _ptr(p, ctypes.c_uint32), cap)
     if r < 0:
         raise ValueError("oracle minimizers rejected k=%d w=%d" % (k, w))

@@ -45,6 +45,10 @@
  *   - an invalid k-mer never wins a window; a window with no valid k-mer
  *     stores nothing; positions are 0-based k-mer start offsets;
  *   - n < w (or fewer than w k-mers) gives no output at all;
+ *   - with ORC_SPLIT, invalid bases split the sequence into segments and only
+ *     windows wholly inside a segment count: a window holding an invalid
+ *     k-mer stores nothing, as a window with no valid k-mer does.  The result
+ *     is that of each segment taken as its own sequence, positions kept;
  *   - the seed pointer table has 2^bits + 1 entries, ptr[j] = number of
  *     entries with key < j, so the hits of key j are ptr[j] .. ptr[j+1] - 1.
  *     The paper's table, whose entry for seed s ends the list of s (the
@@ -65,6 +69,8 @@
 /* Minimizer flags understood by the oracle. */
 #define ORC_FORWARD 1u  /* use the forward k-mer instead of the canonical one */
 #define ORC_IDENTITY 2u /* use the k-mer value itself instead of its hash    */
+#define ORC_SPLIT 4u    /* invalid bases split the sequence: a window holding
+                           an invalid k-mer stores nothing                    */
 
 /* ---------------------------------------------------------------------- */
 /* Sec. 2.2, Eq. 2: the sliding window sum, one left fold of w addends.     */
@@ -252,7 +258,8 @@ static void emit(uint64_t h, uint64_t pos, orc_prev *prev, uint64_t *count,
 }
 
 static int check_args(uint32_t k, uint32_t w, uint32_t flags) {
-    return k >= 1 && k <= 31 && w >= 1 && (flags & ~(ORC_FORWARD | ORC_IDENTITY)) == 0;
+    return k >= 1 && k <= 31 && w >= 1 &&
+           (flags & ~(ORC_FORWARD | ORC_IDENTITY | ORC_SPLIT)) == 0;
 }
 
 /* O(w) per window.  Returns the number of minimizers (entries beyond cap are
@@ -269,10 +276,15 @@ long long oracle_minimizers_naive(const uint8_t *seq, uint64_t n, uint32_t k,
     if (nk >= w) {
         for (uint64_t p = 0; p + w <= nk; ++p) {
             const orc_key *best = NULL;
+            int holds_invalid = 0;
             for (uint64_t j = p; j < p + w; ++j) {
-                if (!keys[j].valid) continue;
+                if (!keys[j].valid) {
+                    holds_invalid = 1;
+                    continue;
+                }
                 if (best == NULL || key_less(&keys[j], best)) best = &keys[j];
             }
+            if ((flags & ORC_SPLIT) && holds_invalid) best = NULL;
             if (best == NULL) { /* no valid k-mer: nothing stored */
                 prev.some = 0;
                 continue;
@@ -299,15 +311,19 @@ static int deque_windows(const uint8_t *seq, uint64_t n, uint32_t k, uint32_t w,
     }
     uint64_t head = 0, tail = 0; /* deque = dq[head, tail), keys increasing */
     orc_prev prev = {0, 0, 0};
+    uint64_t next_clean = 0; /* first window start after the latest invalid k-mer */
     for (uint64_t i = 0; i < nk; ++i) {
         if (keys[i].valid) {
             while (tail > head && key_less(&keys[i], &keys[dq[tail - 1]])) --tail;
             dq[tail++] = i;
+        } else {
+            next_clean = i + 1;
         }
         if (i + 1 >= w) {
             uint64_t p = i + 1 - w; /* window p covers k-mers p .. i */
             while (tail > head && dq[head] < p) ++head;
-            if (tail == head) { /* no valid k-mer in the window */
+            /* no valid k-mer in the window, or (split) an invalid one */
+            if (tail == head || ((flags & ORC_SPLIT) && p < next_clean)) {
                 prev.some = 0;
                 continue;
             }

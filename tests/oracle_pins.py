@@ -517,10 +517,33 @@ def pin_seed_table_invariants(lib):
         assert sorted(zip(po.tolist(), ho.tolist())) == sorted(zip(p.tolist(), h.tolist()))
 
 
+def pin_split_segments(lib):
+    """Split semantics (invalid bases cut the sequence): equal to the string
+    brute force run on every N-free segment, positions shifted by the
+    segment's start; naive and deque agree."""
+    import re
+    rng = np.random.default_rng(13)
+    for trial in range(60):
+        n = int(rng.integers(1, 70))
+        seq = _random_seq(rng, n, n_rate=float(rng.choice([0.0, 0.05, 0.2])), lower_rate=0.1)
+        k = int(rng.integers(1, 5))
+        w = int(rng.integers(1, 6))
+        for canonical, hashed in ((True, True), (False, False)):
+            exp = []
+            for m in re.finditer(r"[ACGTacgt]+", seq):
+                for h, p in brute.minimizers(m.group(0).upper(), k, w, canonical, hashed):
+                    exp.append((h, p + m.start()))
+            for method in ("naive", "deque"):
+                h, p = oracle.minimizers(seq, k, w, canonical=canonical, hashed=hashed,
+                                         method=method, lib=lib, split=True)
+                assert list(zip(h.tolist(), p.tolist())) == exp, (seq, k, w, method)
+
+
 ALL_PINS = [
     pin_sliding_bruteforce, pin_add_prefix_difference, pin_minmax_library,
     pin_minmax_composition, pin_affine_reductions, pin_paper_algorithms, pin_mix64,
     pin_kmers_strings, pin_kmer_strand_symmetry, pin_fig2_worked_example,
     pin_minimizers_bruteforce, pin_minimizers_invariants, pin_minimizer_density, pin_batch,
     pin_fig1_seed_table, pin_seed_table_bruteforce, pin_seed_table_invariants,
+    pin_split_segments,
 ]

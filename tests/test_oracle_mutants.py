@@ -35,6 +35,9 @@ MUTANTS = {
     "seed_key_unshifted": ("next[(hash[i] >> shift) & mask] += 1;", "next[hash[i] & mask] += 1;"),
     "seed_order_reversed": ("        pos_out[next[j]] = pos[i];",
                             "        pos_out[ptr[j + 1] - 1 - (next[j] - ptr[j])] = pos[i];"),
+    "split_clean_off_by_one": ("            next_clean = i + 1;", "            next_clean = i;"),
+    "split_naive_ignored": ("if ((flags & ORC_SPLIT) && holds_invalid) best = NULL;",
+                            "if ((flags & ORC_SPLIT) && holds_invalid && w > 2) best = NULL;"),
 }
 
 
