@@ -78,7 +78,11 @@ enum {
     SWS_KMER_CANONICAL = 0u, /* min(forward, reverse complement)                          */
     SWS_KMER_FORWARD = 1u,   /* forward strand only (the lexicographic seeds of Fig. 2)   */
     SWS_HASH_MIX64 = 0u,     /* hash each k-mer with mix64 (below)                        */
-    SWS_HASH_IDENTITY = 2u   /* use the k-mer value itself                                */
+    SWS_HASH_IDENTITY = 2u,  /* use the k-mer value itself                                */
+    SWS_SPLIT_AT_INVALID = 4u /* minimizers only: invalid bases split the sequence into
+                                 segments and a window holding an invalid k-mer stores
+                                 nothing (each segment as its own sequence, positions
+                                 kept); w <= 32, else SWS_ERR_UNSUPPORTED             */
 };
 
 /*

@@ -170,7 +170,7 @@ def minimizers(seq, k: int, w: int, canonical: bool = True, hashed: bool = True,
 
 
 def minimizers_batch(seqs: np.ndarray, offsets: np.ndarray, k: int, w: int,
-                     canonical: bool = True, hashed: bool = True, lib=None):
+                     canonical: bool = True, hashed: bool = True, lib=None, split: bool = False):
     """Per-read minimizers of reads seqs[offsets[r]:offsets[r+1]].
 
     Returns (hash, pos, read, read_offsets) with read-major order, pos relative
@@ -186,7 +186,7 @@ def minimizers_batch(seqs: np.ndarray, offsets: np.ndarray, k: int, w: int,
     rd = np.zeros(max(cap, 1), dtype=np.uint32)
     ro = np.zeros(nreads + 1, dtype=np.uint64)
     r = lib.oracle_minimizers_batch(_ptr(s, ctypes.c_uint8), _ptr(off, ctypes.c_uint64),
-                                    nreads, k, w, flags_of(canonical, hashed),
+                                    nreads, k, w, flags_of(canonical, hashed, split),
                                     _ptr(h, ctypes.c_uint64), _ptr(p, ctypes.c_uint32),
                                     _ptr(rd, ctypes.c_uint32), cap,
                                     _ptr(ro, ctypes.c_uint64))

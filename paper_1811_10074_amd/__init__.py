@@ -48,8 +48,9 @@ def _need_cuda(t, name):
         raise ValueError("%s must be contiguous" % name)
 
 
-def _flags(canonical: bool, hashed: bool) -> int:
-    return (0 if canonical else _lib.KMER_FORWARD) | (0 if hashed else _lib.HASH_IDENTITY)
+def _flags(canonical: bool, hashed: bool, split: bool = False) -> int:
+    return ((0 if canonical else _lib.KMER_FORWARD) | (0 if hashed else _lib.HASH_IDENTITY)
+            | (_lib.SPLIT_AT_INVALID if split else 0))
 
 
 def window_bound(n: int, k: int, w: int) -> int:
@@ -131,13 +132,18 @@ class MinimizerRunner:
         self.count = torch.zeros(1, dtype=torch.int64, device=device)
         ws = minimizer_workspace_bytes(max_n, k, w)
         self.workspace = torch.empty(max(ws, 8), dtype=torch.uint8, device=device)
+        for name in ("hash", "pos", "count", "workspace"):
+            _need_cuda(getattr(self, name), name)
 
-    def launch(self, seq=None, packed=None, invalid=None, n=None, canonical=True, hashed=True):
+    def launch(self, seq=None, packed=None, invalid=None, n=None, canonical=True, hashed=True,
+               split=False):
         """Enqueue one call on the current stream; results stay on the device
-        (self.hash, self.pos, self.count)."""
+        (self.hash, self.pos, self.count).  split: invalid bases cut the
+        sequence into segments (SWS_SPLIT_AT_INVALID)."""
         lib = _lib.load()
-        fl = _flags(canonical, hashed)
+        fl = _flags(canonical, hashed, split)
         if seq is not None:
+            _need_cuda(seq, "seq")
             n = seq.numel()
             if n > self.max_n:
                 raise ValueError("sequence longer than the runner's max_n")
@@ -148,6 +154,9 @@ class MinimizerRunner:
         else:
             if n is None or n > self.max_n:
                 raise ValueError("n missing or above max_n")
+            _need_cuda(packed, "packed")
+            if invalid is not None:
+                _need_cuda(invalid, "invalid")
             st = lib.sws_minimizers_2bit(_ptr(packed), _ptr(invalid), n, self.k, self.w, fl,
                                          _ptr(self.hash), _ptr(self.pos), self.capacity,
                                          _ptr(self.count), _ptr(self.workspace),
@@ -162,27 +171,29 @@ class MinimizerRunner:
         return self.hash[:c], self.pos[:c]
 
 
-def minimizers(seq, k: int, w: int, canonical: bool = True, hashed: bool = True):
+def minimizers(seq, k: int, w: int, canonical: bool = True, hashed: bool = True,
+               split: bool = False):
     """Deduplicated minimizers of one ASCII sequence: (hash int64[c], pos int32[c])."""
     _need_cuda(seq, "seq")
     r = MinimizerRunner(seq.numel(), k, w, device=seq.device)
-    r.launch(seq=seq, canonical=canonical, hashed=hashed)
+    r.launch(seq=seq, canonical=canonical, hashed=hashed, split=split)
     h, p = r.result()
     return h.clone(), p.clone()
 
 
 def minimizers_2bit(packed, invalid, n: int, k: int, w: int, canonical: bool = True,
-                    hashed: bool = True):
+                    hashed: bool = True, split: bool = False):
     _need_cuda(packed, "packed")
     r = MinimizerRunner(n, k, w, device=packed.device)
-    r.launch(packed=packed, invalid=invalid, n=n, canonical=canonical, hashed=hashed)
+    r.launch(packed=packed, invalid=invalid, n=n, canonical=canonical, hashed=hashed, split=split)
     h, p = r.result()
     return h.clone(), p.clone()
 
 
-def minimizers_batch(seqs, offsets, k: int, w: int, canonical: bool = True, hashed: bool = True):
+def minimizers_batch(seqs, offsets, k: int, w: int, canonical: bool = True, hashed: bool = True,
+                     split: bool = False):
     from .batch import minimizers_batch as _mb
-    return _mb(seqs, offsets, k, w, canonical=canonical, hashed=hashed)
+    return _mb(seqs, offsets, k, w, canonical=canonical, hashed=hashed, split=split)
 
 
 class SeedTableRunner:
@@ -200,9 +211,13 @@ class SeedTableRunner:
         self.hash = (torch.empty(max(max_count, 1), dtype=torch.int64, device=device)
                      if with_hash else None)
         self.workspace = torch.empty(max(int(b.value), 16), dtype=torch.uint8, device=device)
+        for name in ("ptr", "pos", "workspace"):
+            _need_cuda(getattr(self, name), name)
 
     def launch(self, hash_, pos, shift: int):
         """Enqueue on the current stream; results in self.ptr/pos/hash."""
+        _need_cuda(hash_, "hash")
+        _need_cuda(pos, "pos")
         count = pos.numel()
         if hash_.numel() != count or count > self.max_count:
             raise ValueError("hash and pos must have the same length, at most max_count")

@@ -24,6 +24,7 @@ OPS = {"add": 0, "min": 1, "max": 2, "affine": 3}
 PATHS = {"auto": 0, "generic": 1, "log": 2, "prefix": 3, "scalar": 4}
 KMER_FORWARD = 1
 HASH_IDENTITY = 2
+SPLIT_AT_INVALID = 4
 
 _lock = threading.Lock()
 _lib = None

@@ -41,6 +41,13 @@ def _stream():
     return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
 
 
+def _need_cuda(t, name):
+    if not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor, got device %s" % (name, t.device))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
 def window_bound(offsets: np.ndarray, k: int, w: int) -> int:
     """Most minimizers the reads can have: sum over reads of max(0, L-k-w+2)."""
     lens = np.diff(np.asarray(offsets, dtype=np.int64))
@@ -58,11 +65,12 @@ class BatchRunner:
     """Device buffers for one batch of reads (CSR: seqs + offsets)."""
 
     def __init__(self, seqs, offsets_np: np.ndarray, k: int, w: int, canonical=True, hashed=True,
-                 device="cuda"):
+                 device="cuda", split=False):
         torch = _torch()
         off = np.ascontiguousarray(offsets_np, dtype=np.uint64)
         self.k, self.w = k, w
-        self.flags = (0 if canonical else _lib.KMER_FORWARD) | (0 if hashed else _lib.HASH_IDENTITY)
+        self.flags = ((0 if canonical else _lib.KMER_FORWARD) | (0 if hashed else _lib.HASH_IDENTITY)
+                      | (_lib.SPLIT_AT_INVALID if split else 0))
         self.nreads = int(off.size - 1)
         self.total = int(off[-1])
         self.offsets_np = off
@@ -70,6 +78,7 @@ class BatchRunner:
             seqs = torch.from_numpy(np.ascontiguousarray(seqs, dtype=np.uint8)).to(device)
         if seqs.numel() != self.total:
             raise ValueError("seqs has %d bases, offsets say %d" % (seqs.numel(), self.total))
+        _need_cuda(seqs, "seqs")
         self.seqs = seqs
         self.offsets = torch.from_numpy(off.view(np.int64)).to(device)
         self.capacity = window_bound(off, k, w)
@@ -80,6 +89,8 @@ class BatchRunner:
         self.read_out = torch.zeros(self.nreads + 1, dtype=torch.int64, device=device)
         ws = batch_workspace_bytes(self.total, self.nreads, k, w)
         self.workspace = torch.empty(max(ws, 8), dtype=torch.uint8, device=device)
+        for name in ("offsets", "hash", "pos", "read", "read_out", "workspace"):
+            _need_cuda(getattr(self, name), name)
 
     def launch(self):
         st = _lib.load().sws_minimizers_batch(
@@ -99,15 +110,18 @@ class BatchRunner:
         return self.hash[:total], self.pos[:total], self.read[:total], ro
 
 
-def minimizers_batch(seqs, offsets, k: int, w: int, canonical: bool = True, hashed: bool = True):
+def minimizers_batch(seqs, offsets, k: int, w: int, canonical: bool = True, hashed: bool = True,
+                     split: bool = False):
     """Per-read minimizers of reads seqs[offsets[r]:offsets[r+1]] in one launch.
 
     seqs: uint8 device tensor (or numpy array); offsets: host array of
     nreads + 1 non-decreasing values from 0.  Returns (hash int64, pos int32,
     read int32, read_offsets int64[nreads+1]) on the device, read-major."""
-    off = np.asarray(offsets.cpu() if hasattr(offsets, "cpu") else offsets, dtype=np.uint64)
+    torch = _torch()
+    off = np.asarray(offsets.cpu() if torch.is_tensor(offsets) else offsets, dtype=np.uint64)
+    # numpy arrays also carry a .device ("cpu"): only a torch tensor names the device to use
     r = BatchRunner(seqs, off, k, w, canonical, hashed,
-                    device=seqs.device if hasattr(seqs, "device") else "cuda")
+                    device=seqs.device if torch.is_tensor(seqs) else "cuda", split=split)
     r.launch()
     h, p, rd, ro = r.result()
     return h.clone(), p.clone(), rd.clone(), ro.clone()

@@ -10,8 +10,9 @@
 
 namespace {
 
-bool known_flags(uint32_t flags) {
-    return (flags & ~(uint32_t)(SWS_KMER_FORWARD | SWS_HASH_IDENTITY)) == 0u;
+bool known_flags(uint32_t flags, bool windows = true) {
+    const uint32_t ok = SWS_KMER_FORWARD | SWS_HASH_IDENTITY | (windows ? SWS_SPLIT_AT_INVALID : 0u);
+    return (flags & ~ok) == 0u;
 }
 
 // Threads per workgroup of the minimizer kernels, per read-length bucket.
@@ -39,6 +40,9 @@ constexpr uint64_t kMaxPositions = 0xFFFFFFFEull;
 int check_minimizer_args(uint64_t n, uint32_t k, uint32_t w, uint32_t flags) {
     if (k < 1 || k > 31 || w < 1 || !known_flags(flags)) return SWS_ERR_INVALID;
     if (w > kMaxMinimizerWindow) return SWS_ERR_UNSUPPORTED;
+    // the split semantics is built into the w <= 32 (wave-tile) kernels
+    if ((flags & SWS_SPLIT_AT_INVALID) && w > sws::minimizer_wave_max_window())
+        return SWS_ERR_UNSUPPORTED;
     if (n >= kMaxPositions) return SWS_ERR_UNSUPPORTED;
     return SWS_OK;
 }
@@ -150,7 +154,7 @@ int sws_pack2bit(const uint8_t* seq, uint64_t n, uint32_t* packed, uint32_t* inv
 
 int sws_kmers(const uint8_t* seq, uint64_t n, uint32_t k, uint32_t flags, uint64_t* out,
               hipStream_t s) {
-    if (k < 1 || k > 31 || !known_flags(flags)) return SWS_ERR_INVALID;
+    if (k < 1 || k > 31 || !known_flags(flags, false)) return SWS_ERR_INVALID;
     if (k >= 30 && (flags & SWS_HASH_IDENTITY) == 0u) return SWS_ERR_UNSUPPORTED;
     if (n < k) return SWS_OK;
     if (seq == nullptr || out == nullptr) return SWS_ERR_INVALID;

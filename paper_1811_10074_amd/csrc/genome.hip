@@ -652,6 +652,36 @@ __device__ __forceinline__ void doubling_shift(Key (&m)[kR], int lane, uint32_t 
     }
 }
 
+// OR over the `len` bits following each of bits 0..15: bit e of the result is
+// set iff some bit in [e+1, e+len] of x is.  len <= 62 - 15.
+__device__ __forceinline__ uint32_t or_after(uint64_t x, uint32_t len) {
+    if (len == 0) return 0;
+    uint64_t A = x >> 1;
+    uint32_t l = 1;
+    while (2u * l <= len) {
+        A |= A >> l;
+        l *= 2u;
+    }
+    return (uint32_t)((A | (A >> (len - l))) & 0xFFFFu);
+}
+
+// Split semantics (flag 4): invalid bases cut the sequence into segments and
+// a window holding an invalid k-mer stores nothing.  From the lane's invalid
+// k-mer bits (bit e: k-mer 16 lane + e), bit e of the result is set when
+// window 16 lane + e (k-mers e .. e + w - 1) holds one; the next two lanes
+// supply the bits past the lane's run (w <= 32).
+__device__ __forceinline__ uint32_t window_holds_invalid(uint32_t bad, uint32_t w, int lane) {
+    const uint32_t b1 = shfl(bad, lane, 1), b2 = shfl(bad, lane, 2);
+    const uint64_t ext = (uint64_t)bad | ((uint64_t)b1 << 16) | ((uint64_t)b2 << 32);
+    return (bad | or_after(ext, w - 1u)) & 0xFFFFu;
+}
+
+// Bit e set when the window before window 16 lane + e holds an invalid
+// k-mer: the window after such a window is never a duplicate.
+__device__ __forceinline__ uint32_t previous_window_bits(uint32_t wbad, int lane) {
+    return ((wbad << 1) | ((shfl(wbad, lane, -1) >> 15) & 1u)) & 0xFFFFu;
+}
+
 template <int NT, int IN, bool KM64, bool FULL, int FLAGS>
 __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, MinimizerArgs a) {
     constexpr int NWV = NT / kWave;
@@ -679,6 +709,7 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
     const int64_t K0 = p0 - 16;
     Key m[kR];
     uint32_t emit = 0;
+    uint32_t wbad = 0;  // split semantics: windows holding an invalid k-mer
     if (have) {
         RawWords raw;
         fetch_words<IN>(in, K0, lane, raw);
@@ -692,6 +723,7 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
             uint32_t bad;
             lane_kmers<KM64, FLAGS>(code, inv, lane, a.k, (a.flags & 1u) == 0u,
                                     (a.flags & 2u) == 0u, val, bad);
+            if (FLAGS != 0 && (a.flags & kSplitFlag)) wbad = window_holds_invalid(bad, w, lane);
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
                 const bool iv = (bad >> e) & 1u;
@@ -714,13 +746,16 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
         // 4. dedup: window j is stored iff owned, valid and at a new position
         {
             uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
+            const uint32_t pbad = FLAGS != 0 && (a.flags & kSplitFlag)
+                                      ? previous_window_bits(wbad, lane)
+                                      : 0u;
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
                 const uint32_t j = (uint32_t)lane * kR + e;
                 const int64_t p = K0 + (int64_t)j;
                 const bool owned = j >= 16u && j < 16u + a.tw && p < (int64_t)a.nwin;
-                const bool valid = (m[e].tag & kInvalidTag) == 0u;
-                const bool fresh = p == 0 || m[e].tag != prev;
+                const bool valid = (m[e].tag & kInvalidTag) == 0u && !((wbad >> e) & 1u);
+                const bool fresh = p == 0 || m[e].tag != prev || ((pbad >> e) & 1u);
                 emit |= (owned && valid && fresh ? 1u : 0u) << e;
                 prev = m[e].tag;
             }
@@ -797,19 +832,6 @@ __global__ void batch_first_read_kernel(const uint64_t* __restrict__ offsets, ui
     }
 }
 
-// OR over the `len` bits following each of bits 0..15: bit e of the result is
-// set iff some bit in [e+1, e+len] of x is.  len <= 62 - 15.
-__device__ __forceinline__ uint32_t or_after(uint64_t x, uint32_t len) {
-    if (len == 0) return 0;
-    uint64_t A = x >> 1;
-    uint32_t l = 1;
-    while (2u * l <= len) {
-        A |= A >> l;
-        l *= 2u;
-    }
-    return (uint32_t)((A | (A >> (len - l))) & 0xFFFFu);
-}
-
 template <int NT, bool KM64, bool FULL, int FLAGS>
 __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, BatchArgs a) {
     constexpr int NWV = NT / kWave;
@@ -837,6 +859,7 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     const int64_t p0 = (int64_t)(cur * a.tw);
     const int64_t K0 = p0 - 16;
     uint32_t r0 = 0, pre = 0, emit = 0, cnt = 0, incl = 0, sincl = 0, starts = 0;
+    uint32_t wbad = 0;  // split semantics: windows holding an invalid k-mer
     uint64_t B = 0;
     Key m[kR];
     if (has_tile) {
@@ -896,6 +919,7 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
             lane_kmers<KM64, FLAGS>(code, inv, lane, k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u,
                                     val, bad);
             bad |= kcross;
+            if (FLAGS != 0 && (a.flags & kSplitFlag)) wbad = window_holds_invalid(bad, w, lane);
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
                 const bool iv = (bad >> e) & 1u;
@@ -915,13 +939,17 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
         // dedup, restarting at read starts
         {
             uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
+            const uint32_t pbad = FLAGS != 0 && (a.flags & kSplitFlag)
+                                      ? previous_window_bits(wbad, lane)
+                                      : 0u;
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
                 const uint32_t j = (uint32_t)lane * kR + e;
                 const int64_t p = K0 + (int64_t)j;
                 const bool owned = j >= 16u && j < 16u + a.tw && p < (int64_t)a.total;
-                const bool valid = (m[e].tag & kInvalidTag) == 0u && !((wcross >> e) & 1u);
-                const bool fresh = ((B >> e) & 1u) || m[e].tag != prev;
+                const bool valid = (m[e].tag & kInvalidTag) == 0u && !((wcross >> e) & 1u) &&
+                                   !((wbad >> e) & 1u);
+                const bool fresh = ((B >> e) & 1u) || m[e].tag != prev || ((pbad >> e) & 1u);
                 emit |= (owned && valid && fresh ? 1u : 0u) << e;
                 prev = m[e].tag;
             }

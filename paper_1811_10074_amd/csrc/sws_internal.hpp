@@ -29,6 +29,7 @@ enum { kInAscii = 0, kIn2bit = 1 };
 constexpr uint64_t kWsStatusOffset = 256;  // workspace: counter, error flag, then tile status
 constexpr uint32_t kStatusStride = 8;      // status words one per 64-byte line
 constexpr uint32_t kWaveTileGroup = 8;     // wave tiles per workgroup on the w <= 32 path
+constexpr uint32_t kSplitFlag = 4;         // minimizer flag: invalid bases split the sequence
 
 struct GenomeInput {
     int kind;                 // kInAscii or kIn2bit
@@ -77,6 +78,7 @@ int launch_pack2bit(const uint8_t* seq, uint64_t n, uint32_t* packed, uint32_t* 
                     hipStream_t s);
 int launch_kmers(const GenomeInput& in, uint32_t k, uint32_t flags, uint64_t* out, hipStream_t s);
 uint32_t minimizer_tile_windows(uint32_t nt, uint32_t w);
+uint32_t minimizer_wave_max_window();  // largest w of the wave-tile kernels
 uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t w);
 uint64_t minimizer_workspace_bytes(uint64_t ntiles);
 

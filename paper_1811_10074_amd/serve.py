@@ -183,6 +183,8 @@ class GPUExecutor(Executor):
             free, _ = torch.cuda.mem_get_info()
             arena_bytes = int(free * 0.5)
         self.arena_dev = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        if not self.arena_dev.is_cuda:
+            raise ValueError("GPUExecutor needs a CUDA (HIP) device, got %s" % device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(streams)]
         self.free_streams = list(range(streams))
         self.staging = [None] * streams  # grow-only pinned host buffers, one per stream

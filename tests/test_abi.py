@@ -75,13 +75,21 @@ def test_minimizer_validation(lib):
     assert lib.sws_minimizers(*args(bound, 1 << 20, wsp=NULL)) == _lib.SWS_ERR_WORKSPACE
     assert lib.sws_minimizers(*args(bound, 1 << 20, wsp=ctypes.c_void_p(0x10004))) == _lib.SWS_ERR_WORKSPACE
     assert lib.sws_minimizers(*args(bound, 1 << 20, cnt=NULL)) == _lib.SWS_ERR_INVALID
-    assert lib.sws_minimizers(*args(bound, 1 << 20, fl=4)) == _lib.SWS_ERR_INVALID
+    assert lib.sws_minimizers(*args(bound, 1 << 20, fl=8)) == _lib.SWS_ERR_INVALID
     assert lib.sws_minimizers(NULL, n, 15, 10, 0, FAKE, FAKE, bound, FAKE, FAKE, 1 << 20, s) == _lib.SWS_ERR_INVALID
     assert lib.sws_minimizers(FAKE, 1 << 32, 15, 10, 0, FAKE, FAKE, 1 << 33, FAKE, FAKE, 1 << 30, s) == _lib.SWS_ERR_UNSUPPORTED
     assert lib.sws_minimizers_2bit(ctypes.c_void_p(0x10002), NULL, n, 15, 10, 0, FAKE, FAKE, bound, FAKE, FAKE, 1 << 20, s) == _lib.SWS_ERR_INVALID
     assert lib.sws_set_minimizer_block(0, 100) == _lib.SWS_ERR_INVALID
     assert lib.sws_set_minimizer_block(3, 256) == _lib.SWS_ERR_INVALID
     assert lib.sws_set_sliding_waves((1 << 24) + 1) == _lib.SWS_ERR_INVALID
+    # split semantics: minimizers only, w <= 32
+    b2 = ctypes.c_uint64(0)
+    assert lib.sws_minimizers_workspace(1000, 15, 33, ctypes.byref(b2)) == _lib.SWS_OK
+    assert lib.sws_minimizers(FAKE, 1000, 15, 33, 4, FAKE, FAKE, 1 << 20, FAKE, FAKE, 1 << 30,
+                              s) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_kmers(FAKE, 1000, 15, 4, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_minimizers(FAKE, 1000, 15, 10, 8, FAKE, FAKE, 1 << 20, FAKE, FAKE, 1 << 30,
+                              s) == _lib.SWS_ERR_INVALID
     # the prefix-difference path exists for + only
     for op in (1, 2, 3):
         assert lib.sws_sliding_sum_ex(op, 4, FAKE, 100, FAKE, 3, s) == _lib.SWS_ERR_UNSUPPORTED
@@ -106,3 +114,26 @@ def test_minimizer_validation(lib):
     assert st(1000, 16, 48, FAKE, need - 1) == _lib.SWS_ERR_WORKSPACE
     assert st(1000, 16, 48, ctypes.c_void_p(0x10008), need) == _lib.SWS_ERR_WORKSPACE
     assert lib.sws_set_sliding_waves(0) == _lib.SWS_OK
+
+
+def test_binding_rejects_host_buffers():
+    """Host memory never reaches a kernel: the binding refuses CPU tensors and
+    numpy arrays that report a "cpu" device before calling the library."""
+    import numpy as np
+    import torch
+
+    import paper_1811_10074_amd as sws
+    from paper_1811_10074_amd.batch import BatchRunner
+
+    seq = torch.full((100,), ord("A"), dtype=torch.uint8)
+    off = np.array([0, 60, 100], dtype=np.uint64)
+    with pytest.raises(ValueError):
+        BatchRunner(seq, off, 15, 10, device="cpu")
+    with pytest.raises(ValueError):
+        sws.minimizers(seq, 15, 10)
+    with pytest.raises(ValueError):
+        sws.MinimizerRunner(100, 15, 10, device="cpu")
+    with pytest.raises(ValueError):
+        sws.sliding_sum("add", 4, torch.zeros(100, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        sws.seed_table(torch.zeros(10, dtype=torch.int64), torch.zeros(10, dtype=torch.int32), 8)

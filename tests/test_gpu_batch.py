@@ -115,3 +115,24 @@ def test_config4_subsample_bucketed_graph():
             a, e = int(ero[r]), int(ero[r + 1])
             assert np.array_equal(p, ep[a:e]) and np.array_equal(h, eh[a:e]), (rep, r)
         del junk
+
+
+def test_batch_split_at_invalid():
+    """The batched kernel with SWS_SPLIT_AT_INVALID matches the oracle read by
+    read (reads with N runs, uneven lengths)."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    rng = np.random.default_rng(42)
+    lens = np.concatenate([rng.integers(1, 400, 300), rng.integers(1000, 20000, 12)])
+    rng.shuffle(lens)
+    off = np.zeros(lens.size + 1, dtype=np.uint64)
+    np.cumsum(lens, out=off[1:])
+    seqs = inputs.dna(int(off[-1]), seed=43, n_rate=0.01)
+    for k, w in ((15, 10), (19, 19), (7, 32)):
+        h, p, r, ro = sws.minimizers_batch(seqs, off, k, w, split=True)
+        torch.cuda.synchronize()
+        eh, ep, er, ero = oracle.minimizers_batch(seqs, off, k, w, split=True)
+        assert np.array_equal(ro.cpu().numpy().view(np.uint64), ero), (k, w)
+        assert np.array_equal(p.cpu().numpy().view(np.uint32), ep), (k, w)
+        assert np.array_equal(h.cpu().numpy().view(np.uint64), eh), (k, w)
+        assert np.array_equal(r.cpu().numpy().view(np.uint32), er), (k, w)

@@ -172,3 +172,33 @@ def test_config2_full():
     assert np.array_equal(host_u64(h), eh)
     W = n - 15 - 10 + 2
     assert abs(len(ep) / (1 + (W - 1) * 2 / 11) - 1) < 0.005
+
+
+def test_split_at_invalid():
+    """Segment-split N semantics (SWS_SPLIT_AT_INVALID): every window holding
+    an invalid k-mer stores nothing and dedup restarts after it; single
+    sequences with N runs of every length, several k and w <= 32, ASCII and
+    2-bit input."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    rng = np.random.default_rng(41)
+    for n, rate in ((3000, 0.02), (50_000, 0.003), (200_001, 0.01)):
+        s = inputs.dna(n, seed=int(rng.integers(1 << 30)), n_rate=rate)
+        # runs of N as well as single ones
+        for a in rng.integers(0, n - 40, 5):
+            s[a:a + int(rng.integers(1, 40))] = ord("N")
+        t = torch.from_numpy(s).cuda()
+        for k, w in ((15, 10), (5, 1), (19, 19), (11, 32), (31, 2)):
+            for canonical, hashed in ((True, True), (False, True), (True, False)):
+                h, p = sws.minimizers(t, k, w, canonical=canonical, hashed=hashed, split=True)
+                torch.cuda.synchronize()
+                eh, ep = oracle.minimizers(s, k, w, canonical=canonical, hashed=hashed, split=True)
+                assert np.array_equal(p.cpu().numpy().view(np.uint32), ep), (n, k, w)
+                assert np.array_equal(h.cpu().numpy().view(np.uint64), eh), (n, k, w)
+        packed, inv = sws.pack2bit(t)
+        h, p = sws.minimizers_2bit(packed, inv, n, 15, 10, split=True)
+        torch.cuda.synchronize()
+        eh, ep = oracle.minimizers(s, 15, 10, split=True)
+        assert np.array_equal(p.cpu().numpy().view(np.uint32), ep)
+    with pytest.raises(Exception):
+        sws.minimizers(t, 15, 33, split=True)  # w > 32 is unsupported with the flag
