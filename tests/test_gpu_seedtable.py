@@ -108,3 +108,27 @@ def test_runner_reuse_smaller():
         assert np.array_equal(host_u32(r.ptr).astype(np.uint64), eptr)
         assert np.array_equal(host_u32(r.pos[:count]), epo)
         assert np.array_equal(host_u64(r.hash[:count]), eho)
+
+
+@pytest.mark.parametrize("k", [4, 11])
+def test_kmer_counting_composition(k):
+    """K-mer counting as the seed table's pointer differences (Sec. 2.4): the
+    forward k-mers of a sequence with N runs, keyed by their own 2k bits.  The
+    count of every k-mer value equals a histogram of the oracle's k-mers, and
+    each group's positions are that k-mer's occurrences in order."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    seq = inputs.dna(200_003, seed=70 + k, n_rate=0.01)
+    km = sws.kmers(dev(seq, torch), k, canonical=False, hashed=False)
+    ok = km != -1  # invalid k-mers carry 2^64 - 1; the compaction is test plumbing
+    pos = torch.nonzero(ok).flatten().to(torch.int32)
+    keys = km[ok].contiguous()
+    ptr, po, _ = sws.seed_table(keys, pos, 2 * k, 0, with_hash=False)
+    torch.cuda.synchronize()
+    ek = oracle.kmers(seq, k, canonical=False, hashed=False)
+    valid = ek != np.uint64(2**64 - 1)
+    counts = np.bincount(ek[valid].astype(np.int64), minlength=1 << (2 * k))
+    got = host_u32(ptr).astype(np.int64)
+    assert np.array_equal(np.diff(got), counts)
+    order = np.argsort(ek[valid], kind="stable")
+    assert np.array_equal(host_u32(po), np.nonzero(valid)[0][order].astype(np.uint32))
