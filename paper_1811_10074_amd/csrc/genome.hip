@@ -665,15 +665,33 @@ __device__ __forceinline__ uint32_t or_after(uint64_t x, uint32_t len) {
     return (uint32_t)((A | (A >> (len - l))) & 0xFFFFu);
 }
 
-// Split semantics (flag 4): invalid bases cut the sequence into segments and
-// a window holding an invalid k-mer stores nothing.  From the lane's invalid
-// k-mer bits (bit e: k-mer 16 lane + e), bit e of the result is set when
-// window 16 lane + e (k-mers e .. e + w - 1) holds one; the next two lanes
-// supply the bits past the lane's run (w <= 32).
-__device__ __forceinline__ uint32_t window_holds_invalid(uint32_t bad, uint32_t w, int lane) {
+// Invalid k-mer bits of a lane's run and of the next two lanes' runs (bit e:
+// k-mer 16 lane + e), enough for every window that starts in the run (w <= 32).
+__device__ __forceinline__ uint64_t run_bits3(uint32_t bad, int lane) {
     const uint32_t b1 = shfl(bad, lane, 1), b2 = shfl(bad, lane, 2);
-    const uint64_t ext = (uint64_t)bad | ((uint64_t)b1 << 16) | ((uint64_t)b2 << 32);
-    return (bad | or_after(ext, w - 1u)) & 0xFFFFu;
+    return (uint64_t)bad | ((uint64_t)b1 << 16) | ((uint64_t)b2 << 32);
+}
+
+// Split semantics (flag 4): invalid bases cut the sequence into segments and
+// a window holding an invalid k-mer stores nothing.  Bit e of the result is
+// set when window 16 lane + e (k-mers e .. e + w - 1) holds one.
+__device__ __forceinline__ uint32_t window_holds_invalid(uint64_t ext, uint32_t w) {
+    return ((uint32_t)ext | or_after(ext, w - 1u)) & 0xFFFFu;
+}
+
+// Bit e set when window 16 lane + e has no valid k-mer at all (it stores
+// nothing under either semantics).
+__device__ __forceinline__ uint32_t window_all_invalid(uint64_t ext, uint32_t w) {
+    const uint64_t ok = ~ext;
+    return ~((uint32_t)ok | or_after(ok, w - 1u)) & 0xFFFFu;
+}
+
+// Bits of the windows 16 lane + e that a tile stores: 16 <= j < hi (uniform).
+__device__ __forceinline__ uint32_t owned_bits(int64_t hi, int lane) {
+    const int32_t h = (int32_t)(hi < 16 ? 16 : (hi > kWaveKeys ? kWaveKeys : hi));
+    const int32_t b = lane * kR;
+    const int32_t lo_rel = min(max(16 - b, 0), 16), hi_rel = min(max(h - b, 0), 16);
+    return ((1u << hi_rel) - 1u) & ~((1u << lo_rel) - 1u);
 }
 
 // Bit e set when the window before window 16 lane + e holds an invalid
@@ -709,7 +727,6 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
     const int64_t K0 = p0 - 16;
     Key m[kR];
     uint32_t emit = 0;
-    uint32_t wbad = 0;  // split semantics: windows holding an invalid k-mer
     if (have) {
         RawWords raw;
         fetch_words<IN>(in, K0, lane, raw);
@@ -717,19 +734,36 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
         commit_words<IN>(in, K0, lane, raw, code, inv);
         wave_lds_sync();
 
-        // 2. keys
+        // 2. keys.  Without FULL an invalid k-mer gets the all-ones key, which
+        //    no valid k-mer reaches, so it never wins against one; whether a
+        //    window holds any valid k-mer comes from the invalid bits.
+        uint32_t wnone = 0;  // windows without a valid k-mer
+        uint32_t wbad = 0;   // split semantics: windows holding an invalid k-mer
         {
             uint64_t val[kR];
             uint32_t bad;
             lane_kmers<KM64, FLAGS>(code, inv, lane, a.k, (a.flags & 1u) == 0u,
                                     (a.flags & 2u) == 0u, val, bad);
-            if (FLAGS != 0 && (a.flags & kSplitFlag)) wbad = window_holds_invalid(bad, w, lane);
+            const bool split = FLAGS != 0 && (a.flags & kSplitFlag);
+            if (!FULL || split) {
+                const uint64_t ext = run_bits3(bad, lane);
+                if (!FULL) wnone = window_all_invalid(ext, w);
+                if (split) wbad = window_holds_invalid(ext, w);
+            }
+            const uint32_t tbase = (uint32_t)lane * kR;
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
-                const bool iv = (bad >> e) & 1u;
-                m[e].lo = iv ? 0xFFFFFFFFu : (uint32_t)val[e];
-                m[e].hi = iv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
-                m[e].tag = ((uint32_t)lane * kR + e) | (iv ? kInvalidTag : 0u);
+                if (FULL) {
+                    const bool iv = (bad >> e) & 1u;
+                    m[e].lo = iv ? 0xFFFFFFFFu : (uint32_t)val[e];
+                    m[e].hi = iv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
+                    m[e].tag = (tbase + e) | (iv ? kInvalidTag : 0u);
+                } else {
+                    const uint32_t ivm = 0u - ((bad >> e) & 1u);
+                    m[e].lo = (uint32_t)val[e] | ivm;
+                    m[e].hi = (uint32_t)(val[e] >> 32) | ivm;
+                    m[e].tag = tbase + e;
+                }
             }
         }
 
@@ -743,22 +777,30 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
         if (32u <= w) { doubling_step<16, FULL>(m, lane); L = 32; }
         doubling_shift<FULL>(m, lane, w - L);  // 0 <= w - L < L <= 32
 
-        // 4. dedup: window j is stored iff owned, valid and at a new position
+        // 4. dedup, as bit masks over the lane's 16 windows: window j is
+        //    stored iff owned, valid and its minimum sits at another position
+        //    than the previous window's (the first window of the sequence has
+        //    no previous one)
         {
             uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
-            const uint32_t pbad = FLAGS != 0 && (a.flags & kSplitFlag)
-                                      ? previous_window_bits(wbad, lane)
-                                      : 0u;
+            uint32_t fresh = 0;
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
-                const uint32_t j = (uint32_t)lane * kR + e;
-                const int64_t p = K0 + (int64_t)j;
-                const bool owned = j >= 16u && j < 16u + a.tw && p < (int64_t)a.nwin;
-                const bool valid = (m[e].tag & kInvalidTag) == 0u && !((wbad >> e) & 1u);
-                const bool fresh = p == 0 || m[e].tag != prev || ((pbad >> e) & 1u);
-                emit |= (owned && valid && fresh ? 1u : 0u) << e;
+                fresh |= (m[e].tag != prev ? 1u : 0u) << e;
                 prev = m[e].tag;
             }
+            if (p0 == 0 && lane == 1) fresh |= 1u;  // window 0 is j = 16
+            if (FLAGS != 0 && (a.flags & kSplitFlag))
+                fresh |= previous_window_bits(wbad, lane);
+            uint32_t valid = ~(wnone | wbad);
+            if (FULL) {
+#pragma unroll
+                for (int e = 0; e < kR; ++e)
+                    valid &= ~(((m[e].tag & kInvalidTag) != 0u ? 1u : 0u) << e);
+            }
+            const int64_t lim = (int64_t)a.nwin - K0;
+            emit = fresh & valid & owned_bits(lim < 16 + (int64_t)a.tw ? lim : 16 + (int64_t)a.tw,
+                                              lane);
         }
     }
 
@@ -786,14 +828,20 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
     if (have) {
         uint64_t g = s_base + (incl - cnt);
         for (int v = 0; v < wv; ++v) g += s_cnt[v];
+        if (g + cnt > a.capacity) {  // outputs past the capacity are dropped
+            const uint32_t room = g >= a.capacity ? 0u : (uint32_t)(a.capacity - g);
+            while ((uint32_t)__builtin_popcount(emit) > room)
+                emit &= ~(0x80000000u >> __builtin_clz(emit));
+        }
+        uint64_t* ph = a.out_hash + g;
+        uint32_t* pp = a.out_pos + g;
+        const uint32_t pos0 = (uint32_t)K0;  // positions are below 2^32
+        const uint32_t tmask = FULL ? 0x7FFFu : 0xFFFFFFFFu;
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
             if ((emit >> e) & 1u) {
-                if (g < a.capacity) {
-                    a.out_hash[g] = ((uint64_t)m[e].hi << 32) | m[e].lo;
-                    a.out_pos[g] = (uint32_t)(K0 + (int64_t)(m[e].tag & 0x7FFFu));
-                }
-                ++g;
+                *ph++ = ((uint64_t)m[e].hi << 32) | m[e].lo;
+                *pp++ = pos0 + (m[e].tag & tmask);
             }
         }
     }
@@ -859,7 +907,8 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     const int64_t p0 = (int64_t)(cur * a.tw);
     const int64_t K0 = p0 - 16;
     uint32_t r0 = 0, pre = 0, emit = 0, cnt = 0, incl = 0, sincl = 0, starts = 0;
-    uint32_t wbad = 0;  // split semantics: windows holding an invalid k-mer
+    uint32_t wbad = 0;   // split semantics: windows holding an invalid k-mer
+    uint32_t wnone = 0;  // windows without a valid k-mer (FULL = false)
     uint64_t B = 0;
     Key m[kR];
     if (has_tile) {
@@ -919,13 +968,26 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
             lane_kmers<KM64, FLAGS>(code, inv, lane, k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u,
                                     val, bad);
             bad |= kcross;
-            if (FLAGS != 0 && (a.flags & kSplitFlag)) wbad = window_holds_invalid(bad, w, lane);
+            const bool split = FLAGS != 0 && (a.flags & kSplitFlag);
+            if (!FULL || split) {
+                const uint64_t ext = run_bits3(bad, lane);
+                if (!FULL) wnone = window_all_invalid(ext, w);
+                if (split) wbad = window_holds_invalid(ext, w);
+            }
+            const uint32_t tbase = (uint32_t)lane * kR;
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
-                const bool iv = (bad >> e) & 1u;
-                m[e].lo = iv ? 0xFFFFFFFFu : (uint32_t)val[e];
-                m[e].hi = iv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
-                m[e].tag = ((uint32_t)lane * kR + e) | (iv ? kInvalidTag : 0u);
+                if (FULL) {
+                    const bool iv = (bad >> e) & 1u;
+                    m[e].lo = iv ? 0xFFFFFFFFu : (uint32_t)val[e];
+                    m[e].hi = iv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
+                    m[e].tag = (tbase + e) | (iv ? kInvalidTag : 0u);
+                } else {
+                    const uint32_t ivm = 0u - ((bad >> e) & 1u);
+                    m[e].lo = (uint32_t)val[e] | ivm;
+                    m[e].hi = (uint32_t)(val[e] >> 32) | ivm;
+                    m[e].tag = tbase + e;
+                }
             }
         }
         uint32_t L = 1;
@@ -936,23 +998,27 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
         if (32u <= w) { doubling_step<16, FULL>(m, lane); L = 32; }
         doubling_shift<FULL>(m, lane, w - L);
 
-        // dedup, restarting at read starts
+        // dedup, restarting at read starts (bit masks as in the single-sequence
+        // kernel)
         {
             uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
-            const uint32_t pbad = FLAGS != 0 && (a.flags & kSplitFlag)
-                                      ? previous_window_bits(wbad, lane)
-                                      : 0u;
+            uint32_t fresh = (uint32_t)B & 0xFFFFu;
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
-                const uint32_t j = (uint32_t)lane * kR + e;
-                const int64_t p = K0 + (int64_t)j;
-                const bool owned = j >= 16u && j < 16u + a.tw && p < (int64_t)a.total;
-                const bool valid = (m[e].tag & kInvalidTag) == 0u && !((wcross >> e) & 1u) &&
-                                   !((wbad >> e) & 1u);
-                const bool fresh = ((B >> e) & 1u) || m[e].tag != prev || ((pbad >> e) & 1u);
-                emit |= (owned && valid && fresh ? 1u : 0u) << e;
+                fresh |= (m[e].tag != prev ? 1u : 0u) << e;
                 prev = m[e].tag;
             }
+            if (FLAGS != 0 && (a.flags & kSplitFlag))
+                fresh |= previous_window_bits(wbad, lane);
+            uint32_t valid = ~(wnone | wbad | wcross);
+            if (FULL) {
+#pragma unroll
+                for (int e = 0; e < kR; ++e)
+                    valid &= ~(((m[e].tag & kInvalidTag) != 0u ? 1u : 0u) << e);
+            }
+            const int64_t lim = (int64_t)a.total - K0;
+            emit = fresh & valid & owned_bits(lim < 16 + (int64_t)a.tw ? lim : 16 + (int64_t)a.tw,
+                                              lane);
         }
         cnt = (uint32_t)__builtin_popcount(emit);
         starts = (uint32_t)__builtin_popcountll(B & 0xFFFFull);
@@ -998,7 +1064,8 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
                 const int32_t rk = rank0 + __builtin_popcountll(B & ((2ull << e) - 1ull));
                 const uint32_t rr = rid[rk];
                 a.out_hash[g] = ((uint64_t)m[e].hi << 32) | m[e].lo;
-                a.out_pos[g] = (uint32_t)(K0 + (int64_t)(m[e].tag & 0x7FFFu)) - rstart[rk];
+                a.out_pos[g] = (uint32_t)(K0 + (int64_t)(m[e].tag & (FULL ? 0x7FFFu : 0xFFFFu))) -
+                               rstart[rk];
                 a.out_read[g] = rr;
             }
             ++g;
