@@ -202,3 +202,47 @@ def test_split_at_invalid():
         assert np.array_equal(p.cpu().numpy().view(np.uint32), ep)
     with pytest.raises(Exception):
         sws.minimizers(t, 15, 33, split=True)  # w > 32 is unsupported with the flag
+
+
+def _decode_2bit(words, s0, s1):
+    """ASCII bases s0 .. s1 - 1 of a 2-bit word array (16 per word, first base
+    in the top bits)."""
+    idx = np.arange(s0, s1, dtype=np.int64)
+    codes = (words[idx >> 4] >> (30 - 2 * (idx & 15)).astype(np.uint32)) & np.uint32(3)
+    return np.frombuffer(b"ACGT", dtype=np.uint8)[codes]
+
+
+def test_max_length_sampled():
+    """The longest sequence the library takes (2^32 - 3 bases, i.i.d. uniform,
+    as 2-bit words), in the bench's launch configuration.  Stretches around
+    2^31 and at the end of the 32-bit position range are checked against the
+    oracle run on the stretch alone: an entry is decided by the windows that
+    contain it, so entries whose windows all lie inside the stretch must agree.
+    Positions must increase over the whole output, and the count must match the
+    density of random order (R16) within 0.2%."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    n = 0xFFFFFFFD
+    k, w = 15, 10
+    rng = np.random.default_rng(77)
+    words = rng.integers(0, 1 << 32, (n + 15) // 16, dtype=np.uint32)
+    packed = torch.from_numpy(words.view(np.int32)).cuda()
+    r = sws.MinimizerRunner(n, k, w)
+    r.launch(packed=packed, invalid=None, n=n)
+    h, p = r.result()
+    p64 = p.to(torch.int64) & 0xFFFFFFFF
+    assert bool((p64[1:] > p64[:-1]).all())
+    W = n - k - w + 2
+    assert abs(p64.numel() / (1 + (W - 1) * 2 / (w + 1)) - 1) < 0.002
+    for s0, s1 in ((2**31 - 100_000, 2**31 + 100_000), (n - 200_000, n), (0, 100_000)):
+        eh, ep = oracle.minimizers(_decode_2bit(words, s0, s1), k, w)
+        lo, hi = s0 + w - 1, s1 - k - w + 1
+        ep = ep.astype(np.int64) + s0
+        keep = (ep >= lo) & (ep <= hi)
+        ab = torch.searchsorted(p64, torch.tensor([lo, hi + 1], device=p64.device)).cpu().numpy()
+        gp = p64[ab[0]:ab[1]].cpu().numpy()
+        gh = host_u64(h[ab[0]:ab[1]])
+        assert np.array_equal(gp, ep[keep]), (s0, s1)
+        assert np.array_equal(gh, eh[keep]), (s0, s1)
+    del r, h, p, p64, packed
+    torch.cuda.empty_cache()

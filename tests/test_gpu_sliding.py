@@ -244,3 +244,32 @@ def test_long_streams_unaligned(few_waves, waves):
                 y = sws.sliding_sum(op, w, t[off:], path="generic")
                 torch.cuda.synchronize()
                 assert np.array_equal(host_u32(y), oracle.sliding_sum(op, w, base[off:])), (off, w, op)
+
+
+@pytest.mark.parametrize("op", ["add", "min"])
+def test_beyond_2p32_elements_sampled(op):
+    """n = 2^32 + 4099 (past 32-bit element indices, ragged tail), made on the
+    device by a seeded generator; outputs around index 2^32, the last ones and
+    random ones against the oracle, on every path of the op."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    n = (1 << 32) + 4099
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4242)
+    t = torch.randint(-(1 << 31), 1 << 31, (n,), dtype=torch.int32, device="cuda", generator=g)
+    rng = np.random.default_rng(5)
+    for w in (16, 1000):
+        m = n - w + 1
+        idx = np.unique(np.concatenate([np.arange((1 << 32) - w - 3, (1 << 32) + 3),
+                                        np.arange(m - 5, m), rng.integers(0, m, 200)]))
+        it = torch.from_numpy(idx).to("cuda")
+        win = host_u32(t[(it[:, None] + torch.arange(w, device="cuda")).flatten()]).reshape(-1, w)
+        exp = np.array([oracle.sliding_sum(op, w, row)[0] for row in win], dtype=np.uint32)
+        for path in (["generic", "prefix"] if op == "add" else ["generic", "log"]):
+            y = sws.sliding_sum(op, w, t, path=path)
+            got = host_u32(y[it])
+            bad = np.nonzero(got != exp)[0]
+            assert bad.size == 0, (op, w, path, idx[bad[:5]].tolist())
+            del y
+    del t
+    torch.cuda.empty_cache()
