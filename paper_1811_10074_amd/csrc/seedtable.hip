@@ -109,15 +109,18 @@ __global__ __launch_bounds__(kSeedNT) void seed_hist_kernel(SeedBuffers io, uint
     for (int d = lane; d < kDigits; d += kWave) cnt[wv][d] = 0u;
     wave_lds_sync();
     const uint64_t b = blockIdx.x;
-#pragma unroll 4
+    // every load of the tile first, so that their latencies overlap
+    uint32_t key[kSeedRounds];
+#pragma unroll
     for (int r = 0; r < kSeedRounds; ++r) {
         const uint64_t i = b * kSeedTile + tile_slot(wv, r, lane);
-        if (i < count) {
-            uint32_t key;
-            if (HASH || FIRST) key = seed_key(io.hash_in[i], shift, mask);
-            else key = io.key_in[i];
-            atomicAdd(&cnt[wv][(key >> dshift) & 0xFFu], 1u);
-        }
+        key[r] = 0u;
+        if (i < count) key[r] = (HASH || FIRST) ? seed_key(io.hash_in[i], shift, mask) : io.key_in[i];
+    }
+#pragma unroll
+    for (int r = 0; r < kSeedRounds; ++r) {
+        const uint64_t i = b * kSeedTile + tile_slot(wv, r, lane);
+        if (i < count) atomicAdd(&cnt[wv][(key[r] >> dshift) & 0xFFu], 1u);
     }
     __syncthreads();
     for (int d = (int)threadIdx.x; d < kDigits; d += kSeedNT) {
@@ -204,12 +207,18 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
     const uint64_t below = (1ull << lane) - 1ull;
     SeedItem<HASH> item[kSeedRounds];
     uint32_t rank[kSeedRounds];
+    // every load of the tile first: the ranking rounds below are separated by
+    // wave fences, which loads cannot be moved across
+#pragma unroll
+    for (int r = 0; r < kSeedRounds; ++r) {
+        const uint64_t i = b * kSeedTile + tile_slot(wv, r, lane);
+        if (i < count) item[r] = seed_load<FIRST, HASH>(io, i, shift, mask);
+        else item[r] = SeedItem<HASH>{};
+    }
 #pragma unroll
     for (int r = 0; r < kSeedRounds; ++r) {
         const uint64_t i = b * kSeedTile + tile_slot(wv, r, lane);
         const bool valid = i < count;
-        if (valid) item[r] = seed_load<FIRST, HASH>(io, i, shift, mask);
-        else item[r] = SeedItem<HASH>{};
         const uint32_t d = (item[r].key(shift, mask) >> dshift) & 0xFFu;
         // lanes holding the same digit (valid lanes only)
         uint64_t same = __ballot(valid);
