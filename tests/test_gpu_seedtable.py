@@ -132,3 +132,22 @@ def test_kmer_counting_composition(k):
     assert np.array_equal(np.diff(got), counts)
     order = np.argsort(ek[valid], kind="stable")
     assert np.array_equal(host_u32(po), np.nonzero(valid)[0][order].astype(np.uint32))
+
+
+def test_minimizer_counting_forward_lexicographic():
+    """Counting over minimizers (Sec. 1's application) with the Fig. 2
+    semantics: forward-strand, unhashed (lexicographic) k-mers.  The seed table
+    over the minimizers, keyed by the 2k-bit k-mer itself, gives each k-mer's
+    number of minimizer occurrences as ptr[j + 1] - ptr[j]."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    k, w = 9, 6
+    seq = inputs.dna(300_007, seed=91, n_rate=0.005)
+    h, p = sws.minimizers(dev(seq, torch), k, w, canonical=False, hashed=False)
+    ptr, po, _ = sws.seed_table(h, p, 2 * k, 0, with_hash=False)
+    torch.cuda.synchronize()
+    eh, ep = oracle.minimizers(seq, k, w, canonical=False, hashed=False)
+    counts = np.bincount(eh.astype(np.int64), minlength=1 << (2 * k))
+    assert np.array_equal(np.diff(host_u32(ptr).astype(np.int64)), counts)
+    order = np.argsort(eh, kind="stable")
+    assert np.array_equal(host_u32(po), ep[order])
