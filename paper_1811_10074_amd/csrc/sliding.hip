@@ -470,6 +470,137 @@ __global__ __launch_bounds__(NT) void sliding_log_kernel(const uint32_t* __restr
     }
 }
 
+// Log path for w <= 1024, one wavefront per tile and no workgroup barrier.  A
+// wave takes 64 R consecutive inputs with coalesced 16-byte loads, turns them
+// around in its own LDS region so that each lane holds R consecutive ones, and
+// runs the doubling levels 1, 2, 4, ... in registers: a level's shift of S
+// positions reaches S / R lanes up, whose values come by shuffle, all taken
+// before the level writes.  The windows of 2^L go back through the region and
+// the last, runtime-length step reads them at i and i + (w - 2^L) while the
+// outputs leave with coalesced stores.  Tiles overlap by the halo H = w - 1
+// rounded up to 16, so a tile stores 64 R - H outputs; an output reads only
+// inputs of its own tile (the wrapped values the last lanes receive feed only
+// windows past the tile's share).
+constexpr uint32_t kLogWaveSmall = 64;    // w <= this: R = 16
+constexpr uint32_t kLogWaveMaxWindow = 1024;  // w <= this: R = 32
+
+// LDS word of tile position i: runs of 16 at a stride of 20 words, so that the
+// 16-byte accesses of a lane's run (and of 4 consecutive positions) stay
+// aligned and spread over the banks.
+__device__ __forceinline__ uint32_t log_wave_pad(uint32_t i) { return i + 4u * (i >> 4); }
+
+template <class Op, int R, int S>
+__device__ __forceinline__ void log_wave_step(uint32_t (&v)[R], int lane) {
+    uint32_t r[R];
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        const int j = e + S;
+        r[e] = j < R ? v[j] : shfl(v[j % R], lane, j / R);
+    }
+#pragma unroll
+    for (int e = 0; e < R; ++e) v[e] = Op::combine(v[e], r[e]);
+}
+
+__host__ __device__ constexpr uint32_t log_wave_outputs(uint32_t inputs, uint32_t w) {
+    return inputs - ((w - 1u + 15u) & ~15u);
+}
+
+template <class Op, int R>
+__global__ __launch_bounds__(256) void sliding_log_wave_kernel(const uint32_t* __restrict__ x,
+                                                              uint64_t n, uint32_t w,
+                                                              uint32_t* __restrict__ y,
+                                                              uint64_t count, uint64_t ntiles,
+                                                              int vec) {
+    constexpr int NWV = 256 / kWave;
+    constexpr uint32_t IN = kWave * R;  // inputs per wave tile
+    constexpr int C = (int)IN / 256;    // coalesced 16-byte accesses per lane
+    __shared__ __align__(16) uint32_t region[NWV][IN / 16 * 20];
+    const int lane = lane_id();
+    const int wv = wave_id();
+    const uint64_t tile = (uint64_t)blockIdx.x * NWV + (uint64_t)wv;
+    if (tile >= ntiles) return;  // whole waves only; no workgroup barrier follows
+    uint32_t* buf = region[wv];
+    const uint32_t tw = log_wave_outputs(IN, w);
+    const uint64_t t0 = tile * tw;
+    // 1. coalesced loads: positions 256 c + 4 lane
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const uint32_t i = 256u * c + 4u * lane;
+        const uint64_t g = t0 + i;
+        u32x4 q;
+        if (vec && g + 4u <= n) {
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(x + g));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = g + k < n ? x[g + k] : Op::identity();
+        }
+        *reinterpret_cast<u32x4*>(buf + log_wave_pad(i)) = q;
+    }
+    wave_lds_sync();
+    // 2. lane l takes positions R l .. R l + R - 1
+    uint32_t v[R];
+#pragma unroll
+    for (int c = 0; c < R / 4; ++c) {
+        const u32x4 q = *reinterpret_cast<const u32x4*>(buf + log_wave_pad(R * lane + 4u * c));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[4 * c + k] = q[k];
+    }
+    // 3. levels 1, 2, 4, ... while 2s <= w
+    uint32_t p2 = 1;
+    if (2u <= w) { log_wave_step<Op, R, 1>(v, lane); p2 = 2; }
+    if (4u <= w) { log_wave_step<Op, R, 2>(v, lane); p2 = 4; }
+    if (8u <= w) { log_wave_step<Op, R, 4>(v, lane); p2 = 8; }
+    if (16u <= w) { log_wave_step<Op, R, 8>(v, lane); p2 = 16; }
+    if (32u <= w) { log_wave_step<Op, R, 16>(v, lane); p2 = 32; }
+    if (64u <= w) { log_wave_step<Op, R, 32>(v, lane); p2 = 64; }
+    if (R >= 32) {
+        if (128u <= w) { log_wave_step<Op, R, 64>(v, lane); p2 = 128; }
+        if (256u <= w) { log_wave_step<Op, R, 128>(v, lane); p2 = 256; }
+        if (512u <= w) { log_wave_step<Op, R, 256>(v, lane); p2 = 512; }
+        if (1024u <= w) { log_wave_step<Op, R, 512>(v, lane); p2 = 1024; }
+    }
+    // 4. the windows of p2 back into the region (the reads of step 2 are
+    //    done: a wave's LDS operations complete in order)
+#pragma unroll
+    for (int c = 0; c < R / 4; ++c) {
+        u32x4 q;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = v[4 * c + k];
+        *reinterpret_cast<u32x4*>(buf + log_wave_pad(R * lane + 4u * c)) = q;
+    }
+    wave_lds_sync();
+    // 5. y_i = m_i (+) m_{i + shift}, four consecutive outputs per lane and
+    //    access (tw is a multiple of 16, so a group of four is all in or out)
+    const uint32_t shift = w - p2;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const uint32_t i = 256u * c + 4u * lane;
+        if (i >= tw) continue;
+        const uint64_t g = t0 + i;
+        u32x4 q = *reinterpret_cast<const u32x4*>(buf + log_wave_pad(i));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = Op::combine(q[k], buf[log_wave_pad(i + k + shift)]);
+        if (vec && g + 4u <= count) {
+            __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(y + g));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (g + k < count) y[g + k] = q[k];
+        }
+    }
+}
+
+template <class Op, int R>
+static int launch_log_wave(const uint32_t* x, uint64_t n, uint32_t w, uint32_t* y, uint64_t count,
+                           int vec, hipStream_t s) {
+    const uint64_t tw = log_wave_outputs(kWave * R, w);
+    const uint64_t ntiles = (count + tw - 1) / tw;
+    const uint64_t blocks = (ntiles + 3) / 4;
+    hipLaunchKernelGGL((sliding_log_wave_kernel<Op, R>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       x, n, w, y, count, ntiles, vec);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // ---------------------------------------------------------------------------
 // Scalar-input path (Alg. 1 of Sec. 3.1), w <= 64, any associative operator.
 //
@@ -629,13 +760,17 @@ static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64
 
 template <class Op>
 static int launch_log(const void* x, uint64_t n, uint32_t w, void* y, uint64_t count, hipStream_t s) {
+    const int vec = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0 ? 1 : 0;
+    const uint32_t* xi = static_cast<const uint32_t*>(x);
+    uint32_t* yo = static_cast<uint32_t*>(y);
+    if (w <= kLogWaveSmall) return launch_log_wave<Op, 16>(xi, n, w, yo, count, vec, s);
+    if (w <= kLogWaveMaxWindow) return launch_log_wave<Op, 32>(xi, n, w, yo, count, vec, s);
     constexpr int NT = 256;
     // two padded buffers of tile + w - 1 words within 64 KB
     const uint32_t tile = w <= 2048u ? 4096u : 2048u;
     const uint64_t L = tile + w - 1ull;
     const size_t lds = 2ull * (L + L / 16 + 1ull) * sizeof(uint32_t);
     const uint64_t blocks = (count + tile - 1) / tile;
-    const int vec = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0 ? 1 : 0;
     hipLaunchKernelGGL((sliding_log_kernel<Op, NT>), dim3((unsigned)blocks), dim3(NT), lds, s,
                        static_cast<const uint32_t*>(x), n, w, static_cast<uint32_t*>(y), count, tile,
                        vec);
