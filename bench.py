@@ -309,8 +309,8 @@ def profile_run(torch, args):
         n = 1 << 28
         x = torch.from_numpy(inputs.uniform_u32(n, seed=2).view(np.int32)).cuda()
         y = torch.empty(n - 15, dtype=torch.int32, device="cuda")
-        ms, med, _ = time_launches(torch, lambda: sws.sliding_sum("add", 16, x, out=y), args.steps,
-                                   args.warmup)
+        ms, med, _ = time_launches(torch, lambda: sws.sliding_sum("add", 16, x, path="generic", out=y),
+                                   args.steps, args.warmup)
         print(json.dumps({"kernel": "sliding add w=16 n=2^28", "ms_per_step": ms}))
 
 

@@ -117,11 +117,15 @@ int sws_sliding_sum_ex(int op, uint64_t w, const void* x, uint64_t n, void* y, i
     if (((uintptr_t)x | (uintptr_t)y) & (align - 1u)) return SWS_ERR_INVALID;
     const uint64_t count = n - w + 1;
     int use = path;
-    // measured at n = 2^28: the prefix difference matches the generic path up
-    // to w = 256 and is 9-33% faster from w = 1024 on (its work does not grow
-    // with w)
-    if (use == SWS_PATH_AUTO)
-        use = op == SWS_OP_ADD_U32 && w > 512 ? SWS_PATH_PREFIX : SWS_PATH_GENERIC;
+    // measured at n = 2^28: for w <= 64 the one-wave tiles of the prefix
+    // difference (+) and of the doubling (min, max) beat the streaming generic
+    // kernel by 2-7%; the prefix difference matches it up to w = 256 and is
+    // 9-33% faster from w = 1024 on (its work does not grow with w)
+    if (use == SWS_PATH_AUTO) {
+        if (op == SWS_OP_ADD_U32) use = w <= 64 || w > 512 ? SWS_PATH_PREFIX : SWS_PATH_GENERIC;
+        else if (idem) use = w <= 64 ? SWS_PATH_LOG : SWS_PATH_GENERIC;
+        else use = SWS_PATH_GENERIC;
+    }
     if (use == SWS_PATH_LOG) {
         if (w > sws::log_max_window()) return SWS_ERR_UNSUPPORTED;
         return sws::launch_sliding_log(op, x, n, (uint32_t)w, y, count, s) == 0 ? SWS_OK

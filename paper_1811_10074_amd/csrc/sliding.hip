@@ -601,6 +601,88 @@ static int launch_log_wave(const uint32_t* x, uint64_t n, uint32_t w, uint32_t* 
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Prefix-difference path (+ only) for w <= 64, on the same one-wave tiles as
+// the log path: 1024 inputs per wave turned around in LDS into runs of 16 per
+// lane, tiles overlapping by the halo H = w - 1 rounded up to 16.  The running
+// prefix P covers the tile (a common offset cancels in the difference); it
+// goes back to the LDS region and y_i = P_{i+w-1} - P_{i-1} (P_{-1} = 0) leaves
+// with coalesced stores.  (The block prefix/suffix form on these tiles was
+// measured slower than the streaming kernel above and is not used.)
+constexpr uint32_t kPrefixTileMaxWindow = 64;
+
+__global__ __launch_bounds__(256) void sliding_prefix_tile_kernel(const uint32_t* __restrict__ x,
+                                                                 uint64_t n, uint32_t w,
+                                                                 uint32_t* __restrict__ y,
+                                                                 uint64_t count, uint64_t ntiles,
+                                                                 int vec) {
+    constexpr int R = kLogRun;
+    constexpr int NWV = 256 / kWave;
+    constexpr uint32_t IN = kWave * R;  // inputs per wave tile
+    constexpr int C = (int)IN / 256;    // coalesced 16-byte accesses per lane
+    __shared__ __align__(16) uint32_t region[NWV][IN / 16 * 20];
+    const int lane = lane_id();
+    const int wv = wave_id();
+    const uint64_t tile = (uint64_t)blockIdx.x * NWV + (uint64_t)wv;
+    if (tile >= ntiles) return;  // whole waves only; no workgroup barrier follows
+    uint32_t* buf = region[wv];
+    const uint32_t tw = log_wave_outputs(IN, w);
+    const uint64_t t0 = tile * tw;
+    // 1. coalesced loads: positions 256 c + 4 lane
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const uint32_t i = 256u * c + 4u * lane;
+        const uint64_t g = t0 + i;
+        u32x4 q;
+        if (vec && g + 4u <= n) {
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(x + g));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = g + k < n ? x[g + k] : 0u;
+        }
+        *reinterpret_cast<u32x4*>(buf + log_wave_pad(i)) = q;
+    }
+    wave_lds_sync();
+    // 2. lane l takes positions R l .. R l + R - 1 and forms the tile prefix
+    uint32_t v[R];
+#pragma unroll
+    for (int c = 0; c < R / 4; ++c) {
+        const u32x4 q = *reinterpret_cast<const u32x4*>(buf + log_wave_pad(R * lane + 4u * c));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[4 * c + k] = q[k];
+    }
+    slab_prefix<OpAdd, R>(v, (HeadMask<R>)0, (uint32_t)kWave, lane, 0u);
+    // 3. back into LDS (the reads of step 2 are done: a wave's LDS operations
+    //    complete in order)
+#pragma unroll
+    for (int c = 0; c < R / 4; ++c) {
+        u32x4 q;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = v[4 * c + k];
+        *reinterpret_cast<u32x4*>(buf + log_wave_pad(R * lane + 4u * c)) = q;
+    }
+    wave_lds_sync();
+    // 4. four consecutive outputs per lane and access (tw is a multiple of 16)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const uint32_t i = 256u * c + 4u * lane;
+        if (i >= tw) continue;
+        const uint64_t g = t0 + i;
+        u32x4 q;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t before = i + k == 0u ? 0u : buf[log_wave_pad(i + k - 1u)];
+            q[k] = buf[log_wave_pad(i + k + w - 1u)] - before;
+        }
+        if (vec && g + 4u <= count) {
+            __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(y + g));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (g + k < count) y[g + k] = q[k];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Scalar-input path (Alg. 1 of Sec. 3.1), w <= 64, any associative operator.
 //
@@ -809,6 +891,15 @@ int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* 
 int launch_sliding_prefix(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
                           uint64_t tw, hipStream_t s) {
     if (op != kOpAdd) return -2;
+    if (w <= kPrefixTileMaxWindow) {  // one-wave tiles
+        const int vec = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0 ? 1 : 0;
+        const uint64_t tw = log_wave_outputs(kWave * kLogRun, w);
+        const uint64_t ntiles = (count + tw - 1) / tw;
+        hipLaunchKernelGGL(sliding_prefix_tile_kernel, dim3((unsigned)((ntiles + 3) / 4)),
+                           dim3(256), 0, s, static_cast<const uint32_t*>(x), n, w,
+                           static_cast<uint32_t*>(y), count, ntiles, vec);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
     return w > (uint32_t)(kWave * 16) ? launch_generic<OpAdd, 32, 1, true>(x, n, w, y, count, tw, s)
                                       : launch_generic<OpAdd, 16, 2, true>(x, n, w, y, count, tw, s);
 }
