@@ -80,10 +80,17 @@ enum {
     SWS_KMER_FORWARD = 1u,   /* forward strand only (the lexicographic seeds of Fig. 2)   */
     SWS_HASH_MIX64 = 0u,     /* hash each k-mer with mix64 (below)                        */
     SWS_HASH_IDENTITY = 2u,  /* use the k-mer value itself                                */
-    SWS_SPLIT_AT_INVALID = 4u /* minimizers only: invalid bases split the sequence into
-                                 segments and a window holding an invalid k-mer stores
-                                 nothing (each segment as its own sequence, positions
-                                 kept); w <= 32, else SWS_ERR_UNSUPPORTED             */
+    SWS_SPLIT_AT_INVALID = 4u, /* minimizers only: invalid bases split the sequence into
+                                  segments and a window holding an invalid k-mer stores
+                                  nothing (each segment as its own sequence, positions
+                                  kept); w <= 32, else SWS_ERR_UNSUPPORTED            */
+    SWS_WORKSPACE_KEPT = 8u    /* sws_minimizers / sws_minimizers_2bit only: the workspace
+                                  holds what the previous call with this flag left, or
+                                  was zero-filled, and nothing else wrote it since; the
+                                  call then skips clearing it (one kernel launch fewer).
+                                  Call without the flag (or zero-fill) at least once
+                                  every 2^30 calls.  Not a k-mer option: no effect on
+                                  the results                                        */
 };
 
 /*
@@ -186,7 +193,9 @@ int sws_minimizers_workspace(uint64_t n, uint32_t k, uint32_t w, uint64_t *bytes
  *               unusable).
  *   workspace : ws_bytes bytes of device scratch, 8-byte aligned, at least
  *               sws_minimizers_workspace(n, k, w); its contents on entry do
- *               not matter (the call clears what it uses).
+ *               not matter (the call clears what it uses), unless flags holds
+ *               SWS_WORKSPACE_KEPT (see there).  The call leaves it valid for
+ *               a later call with that flag, of any size it is large enough for.
  */
 int sws_minimizers(const uint8_t *seq, uint64_t n, uint32_t k, uint32_t w, uint32_t flags,
                    uint64_t *out_hash, uint32_t *out_pos, uint64_t capacity, uint64_t *d_count,

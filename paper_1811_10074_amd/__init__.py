@@ -131,7 +131,10 @@ class MinimizerRunner:
         self.pos = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=device)
         self.count = torch.zeros(1, dtype=torch.int64, device=device)
         ws = minimizer_workspace_bytes(max_n, k, w)
-        self.workspace = torch.empty(max(ws, 8), dtype=torch.uint8, device=device)
+        # zero-filled once, then kept by the library between calls
+        # (SWS_WORKSPACE_KEPT), which saves clearing it on every call
+        self.workspace = torch.zeros(max(ws, 8), dtype=torch.uint8, device=device)
+        self.calls = 0
         for name in ("hash", "pos", "count", "workspace"):
             _need_cuda(getattr(self, name), name)
 
@@ -142,6 +145,10 @@ class MinimizerRunner:
         sequence into segments (SWS_SPLIT_AT_INVALID)."""
         lib = _lib.load()
         fl = _flags(canonical, hashed, split)
+        # the library asks for a call without the flag at least every 2^30 calls
+        if self.calls % (1 << 29) != 0:
+            fl |= _lib.WORKSPACE_KEPT
+        self.calls += 1
         if seq is not None:
             _need_cuda(seq, "seq")
             n = seq.numel()

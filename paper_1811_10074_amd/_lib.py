@@ -25,6 +25,7 @@ PATHS = {"auto": 0, "generic": 1, "log": 2, "prefix": 3, "scalar": 4}
 KMER_FORWARD = 1
 HASH_IDENTITY = 2
 SPLIT_AT_INVALID = 4
+WORKSPACE_KEPT = 8
 
 _lock = threading.Lock()
 _lib = None

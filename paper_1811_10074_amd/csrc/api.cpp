@@ -10,8 +10,9 @@
 
 namespace {
 
-bool known_flags(uint32_t flags, bool windows = true) {
-    const uint32_t ok = SWS_KMER_FORWARD | SWS_HASH_IDENTITY | (windows ? SWS_SPLIT_AT_INVALID : 0u);
+bool known_flags(uint32_t flags, bool windows = true, bool kept = false) {
+    const uint32_t ok = SWS_KMER_FORWARD | SWS_HASH_IDENTITY |
+                        (windows ? SWS_SPLIT_AT_INVALID : 0u) | (kept ? SWS_WORKSPACE_KEPT : 0u);
     return (flags & ~ok) == 0u;
 }
 
@@ -38,7 +39,7 @@ constexpr uint32_t kMaxMinimizerWindow = 1024;  // keys per wavefront
 constexpr uint64_t kMaxPositions = 0xFFFFFFFEull;
 
 int check_minimizer_args(uint64_t n, uint32_t k, uint32_t w, uint32_t flags) {
-    if (k < 1 || k > 31 || w < 1 || !known_flags(flags)) return SWS_ERR_INVALID;
+    if (k < 1 || k > 31 || w < 1 || !known_flags(flags, true, true)) return SWS_ERR_INVALID;
     if (w > kMaxMinimizerWindow) return SWS_ERR_UNSUPPORTED;
     // the split semantics is built into the w <= 32 (wave-tile) kernels
     if ((flags & SWS_SPLIT_AT_INVALID) && w > sws::minimizer_wave_max_window())
@@ -74,7 +75,7 @@ int minimizers_common(const sws::GenomeInput& in, uint64_t n, uint32_t k, uint32
     memset(&a, 0, sizeof(a));
     a.k = k;
     a.w = w;
-    a.flags = flags;
+    a.flags = flags & ~(uint32_t)SWS_WORKSPACE_KEPT;  // the kernels see the k-mer flags only
     a.tw = tw;
     a.nwin = nwin;
     a.ntiles = ntiles;
@@ -82,7 +83,9 @@ int minimizers_common(const sws::GenomeInput& in, uint64_t n, uint32_t k, uint32
     a.out_pos = out_pos;
     a.capacity = capacity;
     a.d_count = d_count;
-    return sws::launch_minimizers(in, a, nt, workspace, s) == 0 ? SWS_OK : SWS_ERR_DEVICE;
+    return sws::launch_minimizers(in, a, nt, workspace, s, (flags & SWS_WORKSPACE_KEPT) != 0u) == 0
+               ? SWS_OK
+               : SWS_ERR_DEVICE;
 }
 
 }  // namespace

@@ -366,22 +366,37 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v, int lane) {
 // the 64 it moves 64 further back.  Called by all 64 lanes of one wave;
 // returns the prefix in every lane.
 //
+// A status word is flag (2 bits: AGGREGATE 1, INCLUSIVE 2) | epoch (30 bits) |
+// count (32 bits); a word whose epoch is not this call's reads as unpublished,
+// so a workspace needs no clearing between calls (the epoch of the last call
+// sits in the workspace header; a zero-filled header starts at epoch 1).
+//
 // Status words sit one per 64-byte line (kStatusStride words apart): the
 // words of neighbouring participants are written and polled by different
 // compute units at device scope, and sharing a line serializes those
 // accesses.  The status traffic and the distance to the nearest INCLUSIVE
 // word both grow with the number of participants, so the w <= 32 path makes
 // a workgroup of wave tiles one participant.
+constexpr uint32_t kEpochMask = (1u << 30) - 1u;
+
+// This call's epoch, from the last call's (1 .. 2^30 - 1; never 0, so that a
+// zero-filled error word never matches it).
+__device__ __forceinline__ uint32_t call_epoch(const uint64_t* epoch_word) {
+    return (uint32_t)(*epoch_word % kEpochMask) + 1u;
+}
+
 __device__ uint64_t tile_lookback(uint64_t* status, uint64_t tile, uint64_t total, uint32_t* err,
-                                  int lane) {
-    const uint64_t kAgg = 1ull << 62, kInc = 2ull << 62, kVal = (1ull << 62) - 1ull;
+                                  uint32_t epoch, int lane) {
+    const uint64_t kAgg = 1ull << 62, kInc = 2ull << 62, kVal = 0xFFFFFFFFull;
+    const uint64_t tag = (uint64_t)epoch << 32;
     if (tile == 0) {
         if (lane == 0)
-            __hip_atomic_store(&status[0], kInc | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&status[0], kInc | tag | total, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         return 0;
     }
     if (lane == 0)
-        __hip_atomic_store(&status[tile * kStatusStride], kAgg | total, __ATOMIC_RELAXED,
+        __hip_atomic_store(&status[tile * kStatusStride], kAgg | tag | total, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     uint64_t excl = 0;
     int64_t base = (int64_t)tile - 1;
@@ -391,8 +406,9 @@ __device__ uint64_t tile_lookback(uint64_t* status, uint64_t tile, uint64_t tota
         // before participant 0 there is nothing: read as an INCLUSIVE prefix of 0
         const uint64_t s = j >= 0 ? __hip_atomic_load(&status[(uint64_t)j * kStatusStride],
                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                  : kInc;
-        const uint64_t f = s >> 62;
+                                  : kInc | tag;
+        // a word of another call's epoch has not been published in this one
+        const uint64_t f = ((s >> 32) & kEpochMask) == epoch ? s >> 62 : 0ull;
         const uint64_t inc = __ballot(f == 2);
         const uint64_t notready = __ballot(f == 0);
         const int first = inc ? __builtin_ctzll(inc) : kWave;  // nearest INCLUSIVE lane
@@ -402,7 +418,7 @@ __device__ uint64_t tile_lookback(uint64_t* status, uint64_t tile, uint64_t tota
             // launch cannot produce) flags an error instead of hanging.
             if (++spins > (1u << 20)) {
                 if (lane == 0)
-                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(err, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 break;
             }
@@ -415,16 +431,21 @@ __device__ uint64_t tile_lookback(uint64_t* status, uint64_t tile, uint64_t tota
         base -= kWave;
     }
     if (lane == 0)
-        __hip_atomic_store(&status[tile * kStatusStride], kInc | (excl + total), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&status[tile * kStatusStride], kInc | tag | (excl + total),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return excl;
 }
 
-// The count the last tile reports: the total, or all ones if some tile gave
-// up waiting for a predecessor (an internal error the caller must see).
-__device__ __forceinline__ uint64_t final_count(uint32_t* err, uint64_t total) {
+// The count the last tile reports: the total, or all ones if some tile of
+// this call gave up waiting for a predecessor (an internal error the caller
+// must see).  The last tile also records the call's epoch: every tile read the
+// old one before it published, and the last tile has seen every publication.
+__device__ __forceinline__ uint64_t final_count(uint32_t* err, uint64_t* epoch_word,
+                                                uint32_t epoch, uint64_t total) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? ~0ull : total;
+    const bool failed = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+    *epoch_word = epoch;
+    return failed ? ~0ull : total;
 }
 
 template <int NT, int IN, bool KM64, bool FULL>
@@ -577,8 +598,10 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
             ++slot;
         }
     }
+    uint32_t epoch = 0;
     if (wv == 0) {
-        const uint64_t e = tile_lookback(a.status, tile, total, a.err, lane);
+        epoch = call_epoch(a.epoch);
+        const uint64_t e = tile_lookback(a.status, tile, total, a.err, epoch, lane);
         if (lane == 0) s_excl = e;
     }
     __syncthreads();
@@ -590,7 +613,8 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
             a.out_pos[g] = (uint32_t)(K0 + (int64_t)s_tag[i]);
         }
     }
-    if (tid == 0 && tile == a.ntiles - 1) *a.d_count = final_count(a.err, excl + total);
+    if (tid == 0 && tile == a.ntiles - 1)
+        *a.d_count = final_count(a.err, a.epoch, epoch, excl + total);
 }
 
 // ---------------------------------------------------------------------------
@@ -818,10 +842,12 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
     if (wv == 0) {
         const uint32_t c = lane < NWV ? s_cnt[lane] : 0u;
         const uint64_t block_total = lane_value_u64(wave_sum_u64(c, lane), 0);
-        const uint64_t ex = tile_lookback(a.status, blockIdx.x, block_total, a.err, lane);
+        const uint32_t epoch = call_epoch(a.epoch);
+        const uint64_t ex = tile_lookback(a.status, blockIdx.x, block_total, a.err, epoch, lane);
         if (lane == 0) {
             s_base = ex;
-            if (blockIdx.x == gridDim.x - 1) *a.d_count = final_count(a.err, ex + block_total);
+            if (blockIdx.x == gridDim.x - 1)
+                *a.d_count = final_count(a.err, a.epoch, epoch, ex + block_total);
         }
     }
     __syncthreads();
@@ -1043,11 +1069,12 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     if (wv == 0) {
         const uint32_t c = lane < NWV ? s_cnt[lane] : 0u;
         const uint64_t block_total = lane_value_u64(wave_sum_u64(c, lane), 0);
-        const uint64_t ex = tile_lookback(a.status, blockIdx.x, block_total, a.err, lane);
+        const uint32_t epoch = call_epoch(a.epoch);
+        const uint64_t ex = tile_lookback(a.status, blockIdx.x, block_total, a.err, epoch, lane);
         if (lane == 0) {
             s_base = ex;
             if (blockIdx.x == gridDim.x - 1)
-                a.read_out[a.nreads] = final_count(a.err, ex + block_total);
+                a.read_out[a.nreads] = final_count(a.err, a.epoch, epoch, ex + block_total);
         }
     }
     __syncthreads();
@@ -1155,6 +1182,7 @@ int launch_minimizers_batch(const GenomeInput& in, BatchArgs a, uint32_t nt, voi
     uint8_t* ws = static_cast<uint8_t*>(workspace);
     a.err = reinterpret_cast<uint32_t*>(ws + 8);
     a.status = reinterpret_cast<uint64_t*>(ws + kWsStatusOffset);
+    a.epoch = reinterpret_cast<uint64_t*>(ws + 16);
     a.first_read = reinterpret_cast<uint32_t*>(ws + kWsStatusOffset + 8 * kStatusStride * a.ntiles);
     if (launch_zero(reinterpret_cast<uint64_t*>(ws), kWsStatusOffset / 8 + kStatusStride * a.ntiles,
                     s) != 0)
@@ -1239,17 +1267,20 @@ static void launch_min_nt(const GenomeInput& in, const MinimizerArgs& a, bool km
 }
 
 int launch_minimizers(const GenomeInput& in, MinimizerArgs a, uint32_t nt, void* workspace,
-                      hipStream_t s) {
+                      hipStream_t s, bool kept) {
     uint8_t* ws = static_cast<uint8_t*>(workspace);
     a.counter = reinterpret_cast<uint64_t*>(ws);
     a.err = reinterpret_cast<uint32_t*>(ws + 8);
+    a.epoch = reinterpret_cast<uint64_t*>(ws + 16);
     a.status = reinterpret_cast<uint64_t*>(ws + kWsStatusOffset);
     // one status word per look-back participant: a workgroup of wave tiles on
     // the w <= 32 path, a tile (= workgroup) otherwise
     const bool wave_path = a.w <= minimizer_wave_max_window();
     const uint64_t parts = wave_path ? (a.ntiles + kWaveTileGroup - 1) / kWaveTileGroup : a.ntiles;
-    if (launch_zero(reinterpret_cast<uint64_t*>(ws), kWsStatusOffset / 8 + kStatusStride * parts,
-                    s) != 0)
+    // a kept workspace holds the last call's epoch and status words, which
+    // the epoch tells apart from this call's: nothing to clear
+    if (!kept && launch_zero(reinterpret_cast<uint64_t*>(ws),
+                             kWsStatusOffset / 8 + kStatusStride * parts, s) != 0)
         return -1;
     const bool km64 = a.k > 16;
     const bool full = a.k >= 30 && (a.flags & 2u) == 0u;

@@ -51,6 +51,7 @@ struct MinimizerArgs {
     uint64_t* counter;              // workspace
     uint32_t* err;
     uint64_t* status;
+    uint64_t* epoch;                // workspace header: epoch of the last call
 };
 
 struct BatchArgs {
@@ -67,6 +68,7 @@ struct BatchArgs {
     uint32_t* first_read;     // workspace: per tile
     uint64_t* status;         // workspace
     uint32_t* err;            // workspace
+    uint64_t* epoch;          // workspace header: epoch of the last call
 };
 
 int launch_zero(uint64_t* p, uint64_t words, hipStream_t s);
@@ -88,6 +90,6 @@ int launch_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count,
                       uint32_t shift, uint32_t* ptr, uint32_t* pos_out, uint64_t* hash_out,
                       void* workspace, hipStream_t s);
 int launch_minimizers(const GenomeInput& in, MinimizerArgs a, uint32_t nt, void* workspace,
-                      hipStream_t s);
+                      hipStream_t s, bool kept);
 
 }  // namespace sws

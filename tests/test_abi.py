@@ -75,7 +75,7 @@ def test_minimizer_validation(lib):
     assert lib.sws_minimizers(*args(bound, 1 << 20, wsp=NULL)) == _lib.SWS_ERR_WORKSPACE
     assert lib.sws_minimizers(*args(bound, 1 << 20, wsp=ctypes.c_void_p(0x10004))) == _lib.SWS_ERR_WORKSPACE
     assert lib.sws_minimizers(*args(bound, 1 << 20, cnt=NULL)) == _lib.SWS_ERR_INVALID
-    assert lib.sws_minimizers(*args(bound, 1 << 20, fl=8)) == _lib.SWS_ERR_INVALID
+    assert lib.sws_minimizers(*args(bound, 1 << 20, fl=16)) == _lib.SWS_ERR_INVALID
     assert lib.sws_minimizers(NULL, n, 15, 10, 0, FAKE, FAKE, bound, FAKE, FAKE, 1 << 20, s) == _lib.SWS_ERR_INVALID
     assert lib.sws_minimizers(FAKE, 1 << 32, 15, 10, 0, FAKE, FAKE, 1 << 33, FAKE, FAKE, 1 << 30, s) == _lib.SWS_ERR_UNSUPPORTED
     assert lib.sws_minimizers_2bit(ctypes.c_void_p(0x10002), NULL, n, 15, 10, 0, FAKE, FAKE, bound, FAKE, FAKE, 1 << 20, s) == _lib.SWS_ERR_INVALID
@@ -88,8 +88,13 @@ def test_minimizer_validation(lib):
     assert lib.sws_minimizers(FAKE, 1000, 15, 33, 4, FAKE, FAKE, 1 << 20, FAKE, FAKE, 1 << 30,
                               s) == _lib.SWS_ERR_UNSUPPORTED
     assert lib.sws_kmers(FAKE, 1000, 15, 4, FAKE, s) == _lib.SWS_ERR_INVALID
-    assert lib.sws_minimizers(FAKE, 1000, 15, 10, 8, FAKE, FAKE, 1 << 20, FAKE, FAKE, 1 << 30,
+    assert lib.sws_minimizers(FAKE, 1000, 15, 10, 16, FAKE, FAKE, 1 << 20, FAKE, FAKE, 1 << 30,
                               s) == _lib.SWS_ERR_INVALID
+    # a kept workspace is a single-sequence option: k-mers and batches refuse it
+    kept = _lib.WORKSPACE_KEPT
+    assert lib.sws_kmers(FAKE, 1000, 15, kept, FAKE, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_minimizers_batch(FAKE, FAKE, 10, 1000, 15, 10, kept, FAKE, FAKE, FAKE, 1 << 20,
+                                    FAKE, FAKE, 1 << 30, s) == _lib.SWS_ERR_INVALID
     # the prefix-difference path exists for + only
     for op in (1, 2, 3):
         assert lib.sws_sliding_sum_ex(op, 4, FAKE, 100, FAKE, 3, s) == _lib.SWS_ERR_UNSUPPORTED

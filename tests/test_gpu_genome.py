@@ -246,3 +246,28 @@ def test_max_length_sampled():
         assert np.array_equal(gh, eh[keep]), (s0, s1)
     del r, h, p, p64, packed
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("k,w", [(15, 10), (13, 40)])
+def test_kept_workspace_across_calls(k, w):
+    """SWS_WORKSPACE_KEPT: one runner's workspace kept across calls of falling
+    and rising length (the look-back status words of earlier calls stay in it,
+    told apart by their epoch), through the wave (w <= 32) and block (w > 32)
+    kernels, with calls without the flag in between; every call against the
+    oracle."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    from paper_1811_10074_amd import _lib
+    r = sws.MinimizerRunner(400_000, k, w)
+    plan = [(400_000, 0.0), (120_000, 0.01), (3_000, 0.0), (30, 0.0), (400_000, 0.02),
+            (250_001, 0.0), (400_000, 0.0)]
+    for i, (n, n_rate) in enumerate(plan):
+        s = inputs.dna(n, seed=500 + i, n_rate=n_rate)
+        if i == 4:
+            r.calls = 1 << 29  # this call goes without the flag (the periodic clearing)
+        r.launch(seq=seq_dev(torch, s))
+        h, p = r.result()
+        eh, ep = oracle.minimizers(s, k, w)
+        assert np.array_equal(host_u32(p), ep) and np.array_equal(host_u64(h), eh), (i, n)
+    assert r.calls > 1 << 29
+    assert _lib.WORKSPACE_KEPT == 8
