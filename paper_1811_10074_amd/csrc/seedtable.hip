@@ -13,7 +13,8 @@
 // The entries travel through the passes as (hash, pos) when the hashes are
 // wanted in the output (the key is recomputed from the hash), else as
 // (key, pos).  A pass is three launches:
-//   1. digit histogram of each 4096-entry tile (LDS counters per wave);
+//   1. digit histogram of each 8192-entry tile (LDS counters per wave; the
+//      tile is large so that a digit's run in the scatter is ~32 entries long);
 //   2. per digit, an exclusive scan over the tiles (one workgroup per digit),
 //      giving every (digit, tile) its offset inside the digit's range;
 //   3. stable scatter: a tile's entries are ranked within their digit in
@@ -29,7 +30,7 @@ namespace sws {
 
 namespace {
 
-constexpr int kSeedNT = 256;                           // threads per workgroup
+constexpr int kSeedNT = 512;                           // threads per workgroup
 constexpr int kSeedWaves = kSeedNT / kWave;
 constexpr int kSeedRounds = 16;                        // 64-entry rounds per wave
 constexpr uint32_t kSeedTile = kSeedNT * kSeedRounds;  // entries per tile
