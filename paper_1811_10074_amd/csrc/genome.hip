@@ -1196,6 +1196,10 @@ int launch_minimizers_batch(const GenomeInput& in, BatchArgs a, uint32_t nt, voi
         if (!km64) launch_batch_variant<128, false, false>(in, a, s);
         else if (!full) launch_batch_variant<128, true, false>(in, a, s);
         else launch_batch_variant<128, true, true>(in, a, s);
+    } else if (nt == 512) {
+        if (!km64) launch_batch_variant<512, false, false>(in, a, s);
+        else if (!full) launch_batch_variant<512, true, false>(in, a, s);
+        else launch_batch_variant<512, true, true>(in, a, s);
     } else if (nt == 64) {
         if (!km64) launch_batch_variant<64, false, false>(in, a, s);
         else if (!full) launch_batch_variant<64, true, false>(in, a, s);

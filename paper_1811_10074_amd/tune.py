@@ -1,7 +1,7 @@
 """Autotuner for the minimizer kernels' workgroup size per read-length bucket.
 
 For each bucket present in a sample batch it times every candidate block size
-(64, 128, 256 threads: 1, 2 or 4 wavefront tiles per workgroup) with HIP
+(64, 128, 256, 512 threads: 1, 2, 4 or 8 wavefront tiles per workgroup) with HIP
 events and keeps the fastest.  The table is persisted as JSON keyed by GPU
 architecture, library ABI version, k and w, and applied with
 ``sws_set_minimizer_block``.
@@ -16,7 +16,7 @@ import numpy as np
 from . import _lib
 from .batch import BatchRunner, bucket_of_length, set_block
 
-CANDIDATES = (64, 128, 256)
+CANDIDATES = (64, 128, 256, 512)
 DEFAULT_PATH = os.environ.get("SWS_TUNE_FILE",
                               os.path.join(os.path.expanduser("~"), ".cache", "sws", "tune.json"))
 
