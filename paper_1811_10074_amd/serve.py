@@ -24,6 +24,8 @@ from __future__ import annotations
 import collections
 import concurrent.futures
 import ctypes
+import gc
+import os
 import threading
 import time
 from dataclasses import dataclass, field
@@ -173,9 +175,16 @@ class GPUExecutor(Executor):
     batch's bases, offsets, outputs and workspace; S streams (default
     priority) run batches concurrently."""
 
-    def __init__(self, k: int, w: int, arena_bytes: Optional[int] = None, streams: int = 4,
-                 canonical: bool = True, hashed: bool = True, device: str = "cuda"):
+    def __init__(self, k: int, w: int, arena_bytes: Optional[int] = None,
+                 streams: Optional[int] = None, canonical: bool = True, hashed: bool = True,
+                 device: str = "cuda"):
         import torch
+        if streams is None:
+            # one stream per hardware queue besides torch's default stream:
+            # a stream that shares a queue has its copies wait behind another
+            # stream's work (measured: p99 2.2 ms with 4 streams on 4 queues,
+            # 1.1 ms with 3)
+            streams = max(1, int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) - 1)
         self.torch = torch
         self.k, self.w = k, w
         self.flags = (0 if canonical else _lib.KMER_FORWARD) | (0 if hashed else _lib.HASH_IDENTITY)
@@ -190,11 +199,31 @@ class GPUExecutor(Executor):
         self.staging = [None] * streams  # grow-only pinned host buffers, one per stream
         self.lib = _lib.load()
 
-    def _pinned(self, si: int, nbytes: int):
+    def prepare(self, staging_bytes: int):
+        """Before requests arrive: allocate every stream's pinned input
+        staging for the server's largest batch (pinned allocations are slow
+        and stall the device), and run one small copy and fill on every stream
+        (a stream's first use carries a one-time setup cost)."""
+        for si in range(len(self.streams)):
+            self._pinned(si, staging_bytes, exact=True)
+        # one tiny batch through every stream, at the start of the arena (not in
+        # use yet): the same copies and library launches as a real batch
+        tiny = Request(-1, np.frombuffer(b"ACGT" * 16, dtype=np.uint8).copy(),
+                       np.array([0, 64], dtype=np.uint64), 0.0)
+        need = self.footprint(64, 1, window_bound(tiny.offsets, self.k, self.w))
+        if need * len(self.streams) > self.arena_bytes():
+            return
+        handles = [self.start([tiny], i * need) for i in range(len(self.streams))]
+        for h in handles:
+            self.finish(h)
+
+    def _pinned(self, si: int, nbytes: int, exact: bool = False):
         torch = self.torch
         buf = self.staging[si]
         if buf is None or buf.numel() < nbytes:
-            buf = torch.empty(max(nbytes, 1 << 20) * 5 // 4, dtype=torch.uint8, pin_memory=True)
+            # beyond the reservation, powers of two: a buffer regrows rarely
+            size = int(nbytes) if exact else 1 << max(20, (int(nbytes) - 1).bit_length())
+            buf = torch.empty(max(size, 1 << 20), dtype=torch.uint8, pin_memory=True)
             self.staging[si] = buf
         return buf
 
@@ -348,8 +377,16 @@ class RequestTooLarge(ValueError):
 
 
 class Server:
+    """freeze_gc: at start, move every object that exists then out of the
+    cyclic garbage collector's reach (gc.freeze).  A full collection over a
+    large heap holds the interpreter lock for tens of milliseconds, which
+    stalls the scheduler thread in the middle of a batch (measured: one 50 ms
+    request at 200 requests/s); afterwards only objects created while serving
+    are scanned."""
+
     def __init__(self, executor: Executor, k: int, w: int, max_batch_bases: int = 64 << 20,
-                 poll_s: float = 50e-6):
+                 poll_s: float = 50e-6, freeze_gc: bool = True):
+        self.freeze_gc = freeze_gc
         self.ex = executor
         self.k, self.w = k, w
         self.arena = Arena(executor.arena_bytes())
@@ -381,6 +418,15 @@ class Server:
         return q.future
 
     def start(self):
+        if self.freeze_gc:
+            gc.collect()
+            gc.freeze()
+        # the staging a batch of max_batch_bases needs (bases and, at worst,
+        # one offset per base), allocated before the first request
+        prepare = getattr(self.ex, "prepare", None)
+        if prepare is not None:
+            prepare(Arena.round(min(self.max_batch_bases, self.arena.size)) +
+                    8 * (min(self.max_batch_bases, 1 << 20) + 1))
         self.thread = threading.Thread(target=self._loop, name="sws-scheduler", daemon=True)
         self.thread.start()
         return self
