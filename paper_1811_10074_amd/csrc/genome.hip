@@ -47,19 +47,39 @@ __device__ __forceinline__ bool base_valid(uint32_t b) {
     return u == 'A' || u == 'C' || u == 'G' || u == 'T';
 }
 
+// Four ASCII bytes at once: per byte, code = bits 1..2 xor-folded, valid iff
+// the upper-cased byte equals "ACGT"[code] (one byte permute builds the
+// expected bytes).  Returns the 4 codes packed first-base-high in 8 bits and
+// sets bit i of *inv4 for an invalid byte i; invalid bytes get code 0.
+__device__ __forceinline__ uint32_t ascii4(uint32_t x, uint32_t* inv4) {
+    const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    const uint32_t expect = __builtin_amdgcn_perm(0u, 0x54474341u, c);  // 'T' 'G' 'C' 'A'
+    const uint32_t d = (x & 0xDFDFDFDFu) ^ expect;
+    const uint32_t nz = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;  // byte != 0
+    const uint32_t bad = nz >> 7;                                              // 0 or 1 per byte
+    const uint32_t cv = c & ~(bad * 3u);                                       // invalid -> code 0
+    const uint32_t t = bad | (bad >> 7);
+    *inv4 = (t | (t >> 14)) & 0xFu;
+    return ((cv & 3u) << 6) | ((cv >> 4) & 0x30u) | ((cv >> 14) & 0xCu) | (cv >> 24);
+}
+
 // 16 bases starting at `base` (may be negative or run past n): the code word
 // (first base in bits 31..30) and 16 invalid bits (bit i = base + i).  Bases
 // outside [0, n) are invalid with code 0.  Invalid bases get code 0.
 __device__ __forceinline__ void ascii16(const uint8_t* __restrict__ seq, int64_t base, uint64_t n,
                                         bool aligned, uint32_t& code, uint32_t& inv) {
-    uint32_t word[4];
     if (aligned && base >= 0 && (uint64_t)base + 16 <= n) {
+        // one 16-byte load, four bytes per operation
         const uint4 q = *reinterpret_cast<const uint4*>(seq + base);
-        word[0] = q.x;
-        word[1] = q.y;
-        word[2] = q.z;
-        word[3] = q.w;
-    } else {
+        uint32_t i0, i1, i2, i3;
+        const uint32_t b0 = ascii4(q.x, &i0), b1 = ascii4(q.y, &i1);
+        const uint32_t b2 = ascii4(q.z, &i2), b3 = ascii4(q.w, &i3);
+        code = (b0 << 24) | (b1 << 16) | (b2 << 8) | b3;
+        inv = i0 | (i1 << 4) | (i2 << 8) | (i3 << 12);
+        return;
+    }
+    uint32_t word[4];
+    {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             uint32_t v = 0;
@@ -225,22 +245,6 @@ __device__ __forceinline__ void fetch_words(const GenomeInput& in, int64_t K0, i
     }
 }
 
-// Four ASCII bytes at once: per byte, code = bits 1..2 xor-folded, valid iff
-// the upper-cased byte equals "ACGT"[code] (one byte permute builds the
-// expected bytes).  Returns the 4 codes packed first-base-high in 8 bits and
-// sets bit i of *inv4 for an invalid byte i; invalid bytes get code 0.
-__device__ __forceinline__ uint32_t ascii4(uint32_t x, uint32_t* inv4) {
-    const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
-    const uint32_t expect = __builtin_amdgcn_perm(0u, 0x54474341u, c);  // 'T' 'G' 'C' 'A'
-    const uint32_t d = (x & 0xDFDFDFDFu) ^ expect;
-    const uint32_t nz = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;  // byte != 0
-    const uint32_t bad = nz >> 7;                                              // 0 or 1 per byte
-    const uint32_t cv = c & ~(bad * 3u);                                       // invalid -> code 0
-    const uint32_t t = bad | (bad >> 7);
-    *inv4 = (t | (t >> 14)) & 0xFu;
-    return ((cv & 3u) << 6) | ((cv >> 4) & 0x30u) | ((cv >> 14) & 0xCu) | (cv >> 24);
-}
-
 __device__ __forceinline__ void ascii_word(const GenomeInput& in, int64_t base, const uint4& q,
                                            uint32_t& code, uint32_t& inv) {
     if (in.aligned && base >= 0 && (uint64_t)base + 16 <= in.n) {
@@ -300,12 +304,16 @@ __global__ __launch_bounds__(256) void pack2bit_kernel(const uint8_t* __restrict
 // ---------------------------------------------------------------------------
 // kmers: one tile of 16 * NT positions per workgroup.
 // ---------------------------------------------------------------------------
+// LDS index with one pad word per 16 (runs of 16 per thread, conflict-free).
+__device__ __forceinline__ uint32_t pad16(uint32_t i) { return i + (i >> 4); }
+
 template <int NT, int IN, bool KM64>
 __global__ __launch_bounds__(NT) void kmers_kernel(GenomeInput in, uint32_t k, uint32_t flags,
                                                    uint64_t nk, uint64_t* __restrict__ out) {
     constexpr int P = NT * kR;
     constexpr int NW = NT + 2;
     __shared__ uint32_t s_code[NW], s_inv[NW];
+    __shared__ uint64_t s_out[P + P / 16];  // the tile's values, one pad word per 16
     const int tid = (int)threadIdx.x;
     const int64_t K0 = (int64_t)blockIdx.x * P;
     stage_bases<IN>(in, K0, NW, s_code, s_inv, tid, NT);
@@ -313,10 +321,16 @@ __global__ __launch_bounds__(NT) void kmers_kernel(GenomeInput in, uint32_t k, u
     uint64_t val[kR];
     uint32_t bad;
     lane_kmers<KM64>(s_code, s_inv, tid, k, (flags & 1u) == 0u, (flags & 2u) == 0u, val, bad);
-    const uint64_t p = (uint64_t)K0 + (uint64_t)tid * kR;
+    // a thread holds 16 consecutive values: through LDS, so that each store
+    // instruction writes 64 consecutive values
 #pragma unroll
     for (int e = 0; e < kR; ++e)
-        if (p + e < nk) out[p + e] = ((bad >> e) & 1u) ? ~0ull : val[e];
+        s_out[pad16((uint32_t)tid * kR + e)] = ((bad >> e) & 1u) ? ~0ull : val[e];
+    __syncthreads();
+    for (uint32_t j = (uint32_t)tid; j < (uint32_t)P; j += NT) {
+        const uint64_t g = (uint64_t)K0 + j;
+        if (g < nk) out[g] = s_out[pad16(j)];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -345,7 +359,6 @@ struct OpKeyMin {
     static __device__ __forceinline__ Key combine(Key l, Key r) { return less(r, l) ? r : l; }
 };
 
-__device__ __forceinline__ uint32_t pad16(uint32_t i) { return i + (i >> 4); }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v, int lane) {
 #pragma unroll
