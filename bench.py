@@ -401,6 +401,15 @@ def main():
         "input_2bit": {"Gbases/s": round(n / (ms2 / 1e3) / 1e9, 2), "ms_per_step": round(ms2, 5),
                        "same_count": count2 == count},
     }
+    # the standalone steps a3 and a4 on the same sequence
+    msp, _, _ = time_launches(torch, lambda: sws.pack2bit(seq), args.steps, args.warmup)
+    msk, _, _ = time_launches(torch, lambda: sws.kmers(seq, k), args.steps, args.warmup)
+    pack_bytes = n + n // 4 + n // 8  # ASCII in; codes and invalid bits out
+    kmer_bytes = n + 8 * (n - k + 1)  # ASCII in; one u64 per k-mer out
+    line["pack2bit"] = {"us": round(msp * 1e3, 1), "GB/s": round(pack_bytes / msp / 1e6, 1),
+                        "hbm_frac": round(pack_bytes / msp / 1e6 / HBM_PEAK_GBS, 3)}
+    line["kmers_k15"] = {"us": round(msk * 1e3, 1), "GB/s": round(kmer_bytes / msk / 1e6, 1),
+                         "hbm_frac": round(kmer_bytes / msk / 1e6 / HBM_PEAK_GBS, 3)}
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
         line["cpu_baseline"] = cpu_baseline(seq_np, k, w)
