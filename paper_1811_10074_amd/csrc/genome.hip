@@ -66,16 +66,20 @@ __device__ __forceinline__ uint32_t ascii4(uint32_t x, uint32_t* inv4) {
 // 16 bases starting at `base` (may be negative or run past n): the code word
 // (first base in bits 31..30) and 16 invalid bits (bit i = base + i).  Bases
 // outside [0, n) are invalid with code 0.  Invalid bases get code 0.
+// The code word and invalid bits of 16 bases held as 16 bytes.
+__device__ __forceinline__ void ascii16_bytes(const uint4& q, uint32_t& code, uint32_t& inv) {
+    uint32_t i0, i1, i2, i3;
+    const uint32_t b0 = ascii4(q.x, &i0), b1 = ascii4(q.y, &i1);
+    const uint32_t b2 = ascii4(q.z, &i2), b3 = ascii4(q.w, &i3);
+    code = (b0 << 24) | (b1 << 16) | (b2 << 8) | b3;
+    inv = i0 | (i1 << 4) | (i2 << 8) | (i3 << 12);
+}
+
 __device__ __forceinline__ void ascii16(const uint8_t* __restrict__ seq, int64_t base, uint64_t n,
                                         bool aligned, uint32_t& code, uint32_t& inv) {
     if (aligned && base >= 0 && (uint64_t)base + 16 <= n) {
         // one 16-byte load, four bytes per operation
-        const uint4 q = *reinterpret_cast<const uint4*>(seq + base);
-        uint32_t i0, i1, i2, i3;
-        const uint32_t b0 = ascii4(q.x, &i0), b1 = ascii4(q.y, &i1);
-        const uint32_t b2 = ascii4(q.z, &i2), b3 = ascii4(q.w, &i3);
-        code = (b0 << 24) | (b1 << 16) | (b2 << 8) | b3;
-        inv = i0 | (i1 << 4) | (i2 << 8) | (i3 << 12);
+        ascii16_bytes(*reinterpret_cast<const uint4*>(seq + base), code, inv);
         return;
     }
     uint32_t word[4];
@@ -248,11 +252,7 @@ __device__ __forceinline__ void fetch_words(const GenomeInput& in, int64_t K0, i
 __device__ __forceinline__ void ascii_word(const GenomeInput& in, int64_t base, const uint4& q,
                                            uint32_t& code, uint32_t& inv) {
     if (in.aligned && base >= 0 && (uint64_t)base + 16 <= in.n) {
-        uint32_t i0, i1, i2, i3;
-        const uint32_t b0 = ascii4(q.x, &i0), b1 = ascii4(q.y, &i1);
-        const uint32_t b2 = ascii4(q.z, &i2), b3 = ascii4(q.w, &i3);
-        code = (b0 << 24) | (b1 << 16) | (b2 << 8) | b3;
-        inv = i0 | (i1 << 4) | (i2 << 8) | (i3 << 12);
+        ascii16_bytes(q, code, inv);
     } else {
         ascii16(in.seq, base, in.n, false, code, inv);  // edges and unaligned input
     }
@@ -1286,7 +1286,6 @@ static void launch_min_nt(const GenomeInput& in, const MinimizerArgs& a, bool km
 int launch_minimizers(const GenomeInput& in, MinimizerArgs a, uint32_t nt, void* workspace,
                       hipStream_t s, bool kept) {
     uint8_t* ws = static_cast<uint8_t*>(workspace);
-    a.counter = reinterpret_cast<uint64_t*>(ws);
     a.err = reinterpret_cast<uint32_t*>(ws + 8);
     a.epoch = reinterpret_cast<uint64_t*>(ws + 16);
     a.status = reinterpret_cast<uint64_t*>(ws + kWsStatusOffset);

@@ -48,10 +48,11 @@ struct MinimizerArgs {
     uint32_t* out_pos;
     uint64_t capacity;
     uint64_t* d_count;
-    uint64_t* counter;              // workspace
+    // workspace: a 256-byte header (error word at byte 8, the last call's
+    // epoch at byte 16), then the look-back status words
     uint32_t* err;
     uint64_t* status;
-    uint64_t* epoch;                // workspace header: epoch of the last call
+    uint64_t* epoch;
 };
 
 struct BatchArgs {
