@@ -36,7 +36,9 @@
 extern "C" {
 #endif
 
-#define SWS_ABI_VERSION 1u
+/* 2: seed tables, the prefix-difference and scalar-input paths, SWS_SPLIT_AT_INVALID,
+ * SWS_WORKSPACE_KEPT (all additions; no call changed its meaning) */
+#define SWS_ABI_VERSION 2u
 
 typedef enum {
     SWS_OK = 0,

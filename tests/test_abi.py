@@ -25,7 +25,7 @@ def test_exports_every_header_function(lib):
 
 
 def test_version_and_status(lib):
-    assert lib.sws_abi_version() == 1
+    assert lib.sws_abi_version() == 2
     for st in (0, -1, -2, -3, -4, -5):
         assert lib.sws_status_str(st)
     assert b"unknown" in lib.sws_status_str(7)
