@@ -142,3 +142,22 @@ def test_binding_rejects_host_buffers():
         sws.sliding_sum("add", 4, torch.zeros(100, dtype=torch.int32))
     with pytest.raises(ValueError):
         sws.seed_table(torch.zeros(10, dtype=torch.int64), torch.zeros(10, dtype=torch.int32), 8)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No fallback: without the built library every entry point raises."""
+    import subprocess
+    import sys
+    code = (
+        "import sys\n"
+        "from paper_1811_10074_amd import _lib\n"
+        "_lib.LIB_PATH = %r\n"
+        "try:\n"
+        "    _lib.load()\n"
+        "except ImportError as e:\n"
+        "    print('raised:', 'not built' in str(e))\n"
+        "    sys.exit(0)\n"
+        "sys.exit(1)\n" % str(tmp_path / "absent" / "libsws.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       cwd=str(__import__("pathlib").Path(__file__).resolve().parents[1]))
+    assert r.returncode == 0 and "raised: True" in r.stdout, r.stdout + r.stderr
