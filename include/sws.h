@@ -8,7 +8,7 @@
  *       y_i = x_i (+) x_{i+1} (+) ... (+) x_{i+w-1},  i = 0 .. n-w,
  *     exactly w addends per output, for an associative operator (+);
  *   - k-mers of a DNA sequence as a sliding sum of bases under concatenation
- *     (Sec. 2.4), their canonical form and hash (Sec. 4 uses hashed k-mers);
+ *     (Sec. 2.4), their canonical form and hash (Sec. 4 hashes the k-mers);
  *   - minimizer seeds (Sec. 2.4, Fig. 2): for each window of w consecutive
  *     k-mers, the smallest (hash, position) pair; adjacent windows that share
  *     the pair store it once.

@@ -20,7 +20,7 @@
  *                             sum_j code(s_{i+j}) * 4^(k-1-j); the reverse
  *                             complement likewise; canonical = the smaller.
  *   oracle_mix64(_inv)        the fixed invertible xorshift-multiply hash used
- *                             for "hashed k-mers" (Sec. 4).  The paper names
+ *                             for the k-mer hashing of Sec. 4.  The paper names
  *                             no hash: parity unpinned against the paper; it is
  *                             pinned only to its own definition (known answers
  *                             and the inverse).
