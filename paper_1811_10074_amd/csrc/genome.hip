@@ -646,6 +646,24 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
 constexpr int kWaveKeys = kWave * kR;  // 1024 keys per wave tile
 constexpr int kWaveWords = kWaveKeys / 16 + 2;
 
+// The value of the next lane (lane 63 reads lane 0) and of the previous lane
+// (lane 0 reads lane 63), by the whole-wave DPP rotates: the move runs in the
+// VALU instead of a round trip through the LDS crossbar.  Every lane of the
+// wave must be active.
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x134, 0xF, 0xF, false);  // wave_rol:1
+}
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C, 0xF, 0xF, false);  // wave_ror:1
+}
+__device__ __forceinline__ Key from_next_lane(const Key& v) {
+    Key r;
+    r.lo = from_next_lane(v.lo);
+    r.hi = from_next_lane(v.hi);
+    r.tag = from_next_lane(v.tag);
+    return r;
+}
+
 template <bool FULL>
 __device__ __forceinline__ Key key_min(const Key& l, const Key& r) {
     return OpKeyMin<FULL>::combine(l, r);
@@ -654,10 +672,10 @@ __device__ __forceinline__ Key key_min(const Key& l, const Key& r) {
 // One doubling step in registers: m[e] = min(m[e], m[e + S]); a lane reads
 // m[e + S] past its run from the next lane (values taken before any update).
 template <int S, bool FULL>
-__device__ __forceinline__ void doubling_step(Key (&m)[kR], int lane) {
+__device__ __forceinline__ void doubling_step(Key (&m)[kR]) {
     Key nb[S];
 #pragma unroll
-    for (int t = 0; t < S; ++t) nb[t] = shfl(m[t], lane, 1);
+    for (int t = 0; t < S; ++t) nb[t] = from_next_lane(m[t]);
 #pragma unroll
     for (int e = 0; e < kR; ++e) {
         const Key r = (e + S < kR) ? m[e + S] : nb[e + S - kR];
@@ -668,23 +686,23 @@ __device__ __forceinline__ void doubling_step(Key (&m)[kR], int lane) {
 // The last step shifts by w - 2^L, known only at run time: a uniform switch
 // over the 15 possible values keeps every register index static.
 template <bool FULL>
-__device__ __forceinline__ void doubling_shift(Key (&m)[kR], int lane, uint32_t shift) {
+__device__ __forceinline__ void doubling_shift(Key (&m)[kR], uint32_t shift) {
     switch (shift) {
-    case 1: doubling_step<1, FULL>(m, lane); break;
-    case 2: doubling_step<2, FULL>(m, lane); break;
-    case 3: doubling_step<3, FULL>(m, lane); break;
-    case 4: doubling_step<4, FULL>(m, lane); break;
-    case 5: doubling_step<5, FULL>(m, lane); break;
-    case 6: doubling_step<6, FULL>(m, lane); break;
-    case 7: doubling_step<7, FULL>(m, lane); break;
-    case 8: doubling_step<8, FULL>(m, lane); break;
-    case 9: doubling_step<9, FULL>(m, lane); break;
-    case 10: doubling_step<10, FULL>(m, lane); break;
-    case 11: doubling_step<11, FULL>(m, lane); break;
-    case 12: doubling_step<12, FULL>(m, lane); break;
-    case 13: doubling_step<13, FULL>(m, lane); break;
-    case 14: doubling_step<14, FULL>(m, lane); break;
-    case 15: doubling_step<15, FULL>(m, lane); break;
+    case 1: doubling_step<1, FULL>(m); break;
+    case 2: doubling_step<2, FULL>(m); break;
+    case 3: doubling_step<3, FULL>(m); break;
+    case 4: doubling_step<4, FULL>(m); break;
+    case 5: doubling_step<5, FULL>(m); break;
+    case 6: doubling_step<6, FULL>(m); break;
+    case 7: doubling_step<7, FULL>(m); break;
+    case 8: doubling_step<8, FULL>(m); break;
+    case 9: doubling_step<9, FULL>(m); break;
+    case 10: doubling_step<10, FULL>(m); break;
+    case 11: doubling_step<11, FULL>(m); break;
+    case 12: doubling_step<12, FULL>(m); break;
+    case 13: doubling_step<13, FULL>(m); break;
+    case 14: doubling_step<14, FULL>(m); break;
+    case 15: doubling_step<15, FULL>(m); break;
     default: break;
     }
 }
@@ -704,8 +722,8 @@ __device__ __forceinline__ uint32_t or_after(uint64_t x, uint32_t len) {
 
 // Invalid k-mer bits of a lane's run and of the next two lanes' runs (bit e:
 // k-mer 16 lane + e), enough for every window that starts in the run (w <= 32).
-__device__ __forceinline__ uint64_t run_bits3(uint32_t bad, int lane) {
-    const uint32_t b1 = shfl(bad, lane, 1), b2 = shfl(bad, lane, 2);
+__device__ __forceinline__ uint64_t run_bits3(uint32_t bad) {
+    const uint32_t b1 = from_next_lane(bad), b2 = from_next_lane(b1);
     return (uint64_t)bad | ((uint64_t)b1 << 16) | ((uint64_t)b2 << 32);
 }
 
@@ -733,8 +751,8 @@ __device__ __forceinline__ uint32_t owned_bits(int64_t hi, int lane) {
 
 // Bit e set when the window before window 16 lane + e holds an invalid
 // k-mer: the window after such a window is never a duplicate.
-__device__ __forceinline__ uint32_t previous_window_bits(uint32_t wbad, int lane) {
-    return ((wbad << 1) | ((shfl(wbad, lane, -1) >> 15) & 1u)) & 0xFFFFu;
+__device__ __forceinline__ uint32_t previous_window_bits(uint32_t wbad) {
+    return ((wbad << 1) | ((from_prev_lane(wbad) >> 15) & 1u)) & 0xFFFFu;
 }
 
 template <int NT, int IN, bool KM64, bool FULL, int FLAGS>
@@ -783,7 +801,7 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
                                     (a.flags & 2u) == 0u, val, bad);
             const bool split = FLAGS != 0 && (a.flags & kSplitFlag);
             if (!FULL || split) {
-                const uint64_t ext = run_bits3(bad, lane);
+                const uint64_t ext = run_bits3(bad);
                 if (!FULL) wnone = window_all_invalid(ext, w);
                 if (split) wbad = window_holds_invalid(ext, w);
             }
@@ -807,19 +825,19 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
         // 3. window minimum by doubling: levels 1, 2, 4, 8, 16 while 2s <= w,
         //    then one step by w - 2^L
         uint32_t L = 1;
-        if (2u <= w) { doubling_step<1, FULL>(m, lane); L = 2; }
-        if (4u <= w) { doubling_step<2, FULL>(m, lane); L = 4; }
-        if (8u <= w) { doubling_step<4, FULL>(m, lane); L = 8; }
-        if (16u <= w) { doubling_step<8, FULL>(m, lane); L = 16; }
-        if (32u <= w) { doubling_step<16, FULL>(m, lane); L = 32; }
-        doubling_shift<FULL>(m, lane, w - L);  // 0 <= w - L < L <= 32
+        if (2u <= w) { doubling_step<1, FULL>(m); L = 2; }
+        if (4u <= w) { doubling_step<2, FULL>(m); L = 4; }
+        if (8u <= w) { doubling_step<4, FULL>(m); L = 8; }
+        if (16u <= w) { doubling_step<8, FULL>(m); L = 16; }
+        if (32u <= w) { doubling_step<16, FULL>(m); L = 32; }
+        doubling_shift<FULL>(m, w - L);  // 0 <= w - L < L <= 32
 
         // 4. dedup, as bit masks over the lane's 16 windows: window j is
         //    stored iff owned, valid and its minimum sits at another position
         //    than the previous window's (the first window of the sequence has
         //    no previous one)
         {
-            uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
+            uint32_t prev = from_prev_lane(m[kR - 1].tag);
             uint32_t fresh = 0;
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
@@ -828,7 +846,7 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
             }
             if (p0 == 0 && lane == 1) fresh |= 1u;  // window 0 is j = 16
             if (FLAGS != 0 && (a.flags & kSplitFlag))
-                fresh |= previous_window_bits(wbad, lane);
+                fresh |= previous_window_bits(wbad);
             uint32_t valid = ~(wnone | wbad);
             if (FULL) {
 #pragma unroll
@@ -1009,7 +1027,7 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
             bad |= kcross;
             const bool split = FLAGS != 0 && (a.flags & kSplitFlag);
             if (!FULL || split) {
-                const uint64_t ext = run_bits3(bad, lane);
+                const uint64_t ext = run_bits3(bad);
                 if (!FULL) wnone = window_all_invalid(ext, w);
                 if (split) wbad = window_holds_invalid(ext, w);
             }
@@ -1030,17 +1048,17 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
             }
         }
         uint32_t L = 1;
-        if (2u <= w) { doubling_step<1, FULL>(m, lane); L = 2; }
-        if (4u <= w) { doubling_step<2, FULL>(m, lane); L = 4; }
-        if (8u <= w) { doubling_step<4, FULL>(m, lane); L = 8; }
-        if (16u <= w) { doubling_step<8, FULL>(m, lane); L = 16; }
-        if (32u <= w) { doubling_step<16, FULL>(m, lane); L = 32; }
-        doubling_shift<FULL>(m, lane, w - L);
+        if (2u <= w) { doubling_step<1, FULL>(m); L = 2; }
+        if (4u <= w) { doubling_step<2, FULL>(m); L = 4; }
+        if (8u <= w) { doubling_step<4, FULL>(m); L = 8; }
+        if (16u <= w) { doubling_step<8, FULL>(m); L = 16; }
+        if (32u <= w) { doubling_step<16, FULL>(m); L = 32; }
+        doubling_shift<FULL>(m, w - L);
 
         // dedup, restarting at read starts (bit masks as in the single-sequence
         // kernel)
         {
-            uint32_t prev = shfl(m[kR - 1].tag, lane, -1);
+            uint32_t prev = from_prev_lane(m[kR - 1].tag);
             uint32_t fresh = (uint32_t)B & 0xFFFFu;
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
@@ -1048,7 +1066,7 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
                 prev = m[e].tag;
             }
             if (FLAGS != 0 && (a.flags & kSplitFlag))
-                fresh |= previous_window_bits(wbad, lane);
+                fresh |= previous_window_bits(wbad);
             uint32_t valid = ~(wnone | wbad | wcross);
             if (FULL) {
 #pragma unroll
