@@ -77,6 +77,26 @@ def test_kmers(k):
         sws.kmers(seq_dev(torch, "ACGT" * 20), 30, hashed=True)
 
 
+@pytest.mark.parametrize("k", [15, 21])
+def test_kmers_output_not_16_byte_aligned(k):
+    """An output 8 bytes past a 16-byte boundary takes the one-value-per-store
+    kernel; values are the same."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    from paper_1811_10074_amd import _lib
+    n = 3 * TILE + 5
+    s = inputs.dna(n, seed=77 + k, n_rate=0.02)
+    buf = torch.full((n - k + 3,), 7, dtype=torch.int64, device="cuda")
+    out = buf[1:n - k + 2]
+    assert out.data_ptr() % 16 == 8
+    seq = seq_dev(torch, s)
+    sws.check(_lib.load().sws_kmers(seq.data_ptr(), n, k, 0, out.data_ptr(), sws._stream()), "sws_kmers")
+    torch.cuda.synchronize()
+    got = host_u64(buf)
+    assert np.array_equal(got[1:n - k + 2], oracle.kmers(s, k, canonical=True, hashed=True)), k
+    assert got[0] == 7 and got[-1] == 7  # nothing written outside the output
+
+
 def test_fig2_worked_example():
     torch = torch_cuda()
     g = oracle_pins.read_golden("fig2_worked_example.txt")
