@@ -689,6 +689,7 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
 // the left operand on ties, so the leftmost position wins.
 // ---------------------------------------------------------------------------
 constexpr int kWaveKeys = kWave * kR;  // 1024 keys per wave tile
+constexpr uint32_t kStage = 512;       // outputs per round of a wave's store compaction
 constexpr int kWaveWords = kWaveKeys / 16 + 2;
 
 // The value of the next lane (lane 63 reads lane 0) and of the previous lane
@@ -807,6 +808,8 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
     __shared__ uint32_t s_code[NWV][kWaveWords], s_inv[NWV][kWaveWords];
     __shared__ uint32_t s_cnt[NWV];  // stores per wave tile
     __shared__ uint64_t s_base;      // stores before the workgroup
+    __shared__ uint64_t s_stage_hash[NWV][kStage];
+    __shared__ uint32_t s_stage_pos[NWV][kStage];
 
     const int lane = lane_id();
     const int wv = wave_id();
@@ -928,23 +931,41 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
     }
     __syncthreads();
     if (have) {
-        uint64_t g = s_base + (incl - cnt);
-        for (int v = 0; v < wv; ++v) g += s_cnt[v];
-        if (g + cnt > a.capacity) {  // outputs past the capacity are dropped
-            const uint32_t room = g >= a.capacity ? 0u : (uint32_t)(a.capacity - g);
-            while ((uint32_t)__builtin_popcount(emit) > room)
-                emit &= ~(0x80000000u >> __builtin_clz(emit));
-        }
-        uint64_t* ph = a.out_hash + g;
-        uint32_t* pp = a.out_pos + g;
+        // Compaction through a wave-private LDS buffer: lane l writes its
+        // outputs at their ranks within the wave, then the wave copies the
+        // buffer out with consecutive lanes on consecutive outputs.  Stored
+        // straight from the lanes' runs, each store instruction would scatter
+        // a few values per lane over the wave's whole output range; this way
+        // measured 0.89 of that time (0.85 from 2-bit input).  A wave with
+        // more than kStage outputs takes several rounds.
+        uint64_t* sh = s_stage_hash[wv];
+        uint32_t* sp = s_stage_pos[wv];
+        uint64_t gw = s_base;  // the wave's first output
+        for (int v = 0; v < wv; ++v) gw += s_cnt[v];
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+        uint32_t lim = total;  // outputs past the capacity are dropped
+        if (gw + total > a.capacity) lim = gw >= a.capacity ? 0u : (uint32_t)(a.capacity - gw);
         const uint32_t pos0 = (uint32_t)K0;  // positions are below 2^32
         const uint32_t tmask = FULL ? 0x7FFFu : 0xFFFFFFFFu;
+        for (uint32_t c = 0; c < lim; c += kStage) {
+            uint32_t j = incl - cnt - c;  // rank - c, mod 2^32
 #pragma unroll
-        for (int e = 0; e < kR; ++e) {
-            if ((emit >> e) & 1u) {
-                *ph++ = ((uint64_t)m[e].hi << 32) | m[e].lo;
-                *pp++ = pos0 + (m[e].tag & tmask);
+            for (int e = 0; e < kR; ++e) {
+                if ((emit >> e) & 1u) {
+                    if (j < kStage) {
+                        sh[j] = ((uint64_t)m[e].hi << 32) | m[e].lo;
+                        sp[j] = pos0 + (m[e].tag & tmask);
+                    }
+                    ++j;
+                }
             }
+            wave_lds_sync();
+            const uint32_t nc = min(kStage, lim - c);
+            for (uint32_t r = (uint32_t)lane; r < nc; r += kWave) {
+                a.out_hash[gw + c + r] = sh[r];
+                a.out_pos[gw + c + r] = sp[r];
+            }
+            wave_lds_sync();
         }
     }
 }
