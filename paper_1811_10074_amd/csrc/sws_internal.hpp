@@ -28,7 +28,7 @@ int launch_sliding_log(int op, const void* x, uint64_t n, uint32_t w, void* y, u
 enum { kInAscii = 0, kIn2bit = 1 };
 constexpr uint64_t kWsStatusOffset = 256;  // workspace: counter, error flag, then tile status
 constexpr uint32_t kStatusStride = 8;      // status words one per 64-byte line
-constexpr uint32_t kWaveTileGroup = 8;     // wave tiles per workgroup on the w <= 32 path
+constexpr uint32_t kWaveTileGroup = 4;     // wave tiles per workgroup on the w <= 32 path
 constexpr uint32_t kSplitFlag = 4;         // minimizer flag: invalid bases split the sequence
 
 struct GenomeInput {
