@@ -136,3 +136,29 @@ def test_batch_split_at_invalid():
         assert np.array_equal(p.cpu().numpy().view(np.uint32), ep), (k, w)
         assert np.array_equal(h.cpu().numpy().view(np.uint64), eh), (k, w)
         assert np.array_equal(r.cpu().numpy().view(np.uint32), er), (k, w)
+
+
+def test_truncated_capacity():
+    """A capacity below the total: the first `capacity` entries are the
+    oracle's, nothing is written at or past it, and the offsets still hold
+    the full totals."""
+    torch = torch_cuda()
+    from paper_1811_10074_amd import batch
+    k, w = 15, 10
+    seqs, off = make_batch(np.random.default_rng(5).integers(0, 5000, 60), seed=41)
+    eh, ep, er, ero = oracle.minimizers_batch(seqs, off, k, w)
+    r = batch.BatchRunner(torch.from_numpy(seqs).cuda(), off, k, w)
+    assert r.capacity > eh.size > 1000
+    for cap in (eh.size // 3, 1):
+        r.capacity = cap
+        r.hash.fill_(-5)
+        r.pos.fill_(-5)
+        r.read.fill_(-5)
+        r.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(r.read_out.cpu().numpy().view(np.uint64), ero), cap
+        assert np.array_equal(host_u64(r.hash[:cap]), eh[:cap]), cap
+        assert np.array_equal(host_u32(r.pos[:cap]), ep[:cap]), cap
+        assert np.array_equal(host_u32(r.read[:cap]), er[:cap]), cap
+        assert bool((r.hash[cap:] == -5).all()) and bool((r.pos[cap:] == -5).all()), cap
+        assert bool((r.read[cap:] == -5).all()), cap
