@@ -196,7 +196,10 @@ class GPUExecutor(Executor):
             raise ValueError("GPUExecutor needs a CUDA (HIP) device, got %s" % device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(streams)]
         self.free_streams = list(range(streams))
-        self.staging = [None] * streams  # grow-only pinned host buffers, one per stream
+        # grow-only pinned host buffers, one per stream: the batch's bases and
+        # offsets on the way in, its minimizers on the way out
+        self.staging = [None] * streams
+        self.out_staging = [None] * streams
         self.lib = _lib.load()
 
     def prepare(self, staging_bytes: int):
@@ -204,8 +207,12 @@ class GPUExecutor(Executor):
         staging for the server's largest batch (pinned allocations are slow
         and stall the device), and run one small copy and fill on every stream
         (a stream's first use carries a one-time setup cost)."""
+        # outputs: 12 bytes per minimizer, reserved for a density of 3/(w+1)
+        # (the expected density is about 2/(w+1)); more grows the buffer
+        out_bytes = 12 * max(1 << 16, staging_bytes * 3 // (self.w + 1))
         for si in range(len(self.streams)):
             self._pinned(si, staging_bytes, exact=True)
+            self._pinned_out(si, out_bytes, exact=True)
         # one tiny batch through every stream, at the start of the arena (not in
         # use yet): the same copies and library launches as a real batch
         tiny = Request(-1, np.frombuffer(b"ACGT" * 16, dtype=np.uint8).copy(),
@@ -217,15 +224,20 @@ class GPUExecutor(Executor):
         for h in handles:
             self.finish(h)
 
-    def _pinned(self, si: int, nbytes: int, exact: bool = False):
-        torch = self.torch
-        buf = self.staging[si]
+    def _grow(self, bufs, si: int, nbytes: int, exact: bool):
+        buf = bufs[si]
         if buf is None or buf.numel() < nbytes:
             # beyond the reservation, powers of two: a buffer regrows rarely
             size = int(nbytes) if exact else 1 << max(20, (int(nbytes) - 1).bit_length())
-            buf = torch.empty(max(size, 1 << 20), dtype=torch.uint8, pin_memory=True)
-            self.staging[si] = buf
+            buf = self.torch.empty(max(size, 1 << 20), dtype=self.torch.uint8, pin_memory=True)
+            bufs[si] = buf
         return buf
+
+    def _pinned(self, si: int, nbytes: int, exact: bool = False):
+        return self._grow(self.staging, si, nbytes, exact)
+
+    def _pinned_out(self, si: int, nbytes: int, exact: bool = False):
+        return self._grow(self.out_staging, si, nbytes, exact)
 
     def slots(self) -> int:
         return len(self.streams)
@@ -253,26 +265,34 @@ class GPUExecutor(Executor):
 
     def start(self, reqs, slot):
         torch = self.torch
-        seqs, off = _concat(reqs)
-        nreads, nbases = off.size - 1, int(off[-1])
-        bound = window_bound(off, self.k, self.w)
-        lay, _ = self._layout(nbases, nreads, bound)
+        nreads = sum(q.nreads for q in reqs)
+        nbases = sum(q.nbases for q in reqs)
         si = self.free_streams.pop()
         stream = self.streams[si]
         base = self.arena_dev.data_ptr() + slot
+
+        # concatenate bases and offsets straight into this stream's pinned
+        # buffer, one copy per request (the previous batch on this stream has
+        # finished, so the buffer is free)
+        ob = Arena.round(nbases)
+        pin = self._pinned(si, ob + 8 * (nreads + 1))
+        pin_np = pin.numpy()
+        off = pin_np[ob:ob + 8 * (nreads + 1)].view(np.uint64)
+        off[0] = 0
+        b0, r0 = 0, 0
+        for q in reqs:
+            pin_np[b0:b0 + q.nbases] = q.seqs
+            np.add(q.offsets[1:], np.uint64(b0), out=off[r0 + 1:r0 + q.nreads + 1])
+            b0 += q.nbases
+            r0 += q.nreads
+        bound = window_bound(off, self.k, self.w)
+        lay, _ = self._layout(nbases, nreads, bound)
 
         def view(name, dtype, count):
             o, _n = lay[name]
             t = self.arena_dev[slot + o: slot + o + count * np.dtype(dtype).itemsize]
             return t
 
-        # stage bases and offsets in this stream's pinned buffer (the previous
-        # batch on this stream has finished, so the buffer is free)
-        pin = self._pinned(si, Arena.round(nbases) + 8 * (nreads + 1))
-        pin_np = pin.numpy()
-        pin_np[:nbases] = seqs
-        ob = Arena.round(nbases)
-        pin_np[ob:ob + 8 * (nreads + 1)] = off.view(np.uint8)
         with torch.cuda.stream(stream):
             if nbases:
                 view("seqs", np.uint8, nbases).copy_(pin[:nbases], non_blocking=True)
@@ -312,9 +332,18 @@ class GPUExecutor(Executor):
             total = int(ro[-1])
             if total == 0xFFFFFFFFFFFFFFFF or total > handle["bound"]:
                 raise _lib.SwsError(_lib.SWS_ERR_DEVICE, "batch kernel reported an internal error")
-            h = dev("hash", total, torch.int64).cpu().numpy().view(np.uint64)
-            p = dev("pos", total, torch.int32).cpu().numpy().view(np.uint32)
-        return _split(handle["reqs"], h, p, ro)
+            # through this stream's pinned buffer: a copy to pageable memory
+            # measured several times slower for megabyte outputs
+            out = self._pinned_out(handle["stream"], 12 * total)
+            out[:8 * total].copy_(dev("hash", total, torch.int64).view(torch.uint8),
+                                  non_blocking=True)
+            out[8 * total:12 * total].copy_(dev("pos", total, torch.int32).view(torch.uint8),
+                                            non_blocking=True)
+            stream.synchronize()
+        o = out.numpy()
+        h = o[:8 * total].view(np.uint64)
+        p = o[8 * total:12 * total].view(np.uint32)
+        return _split(handle["reqs"], h, p, ro)  # copies out of the pinned buffer
 
 
 # ---------------------------------------------------------------------------
