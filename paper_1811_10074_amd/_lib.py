@@ -75,7 +75,6 @@ def load():
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise ImportError("libsws.so is not built (%s); run "
-                                  "`python -c 'import __graft_entry__ as g; g.build()'` or "
                                   "`python paper_1811_10074_amd/build.py`" % LIB_PATH)
             lib = ctypes.CDLL(LIB_PATH)
             for name, (res, args) in _SIGNATURES.items():
