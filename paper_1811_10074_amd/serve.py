@@ -207,9 +207,10 @@ class GPUExecutor(Executor):
         staging for the server's largest batch (pinned allocations are slow
         and stall the device), and run one small copy and fill on every stream
         (a stream's first use carries a one-time setup cost)."""
-        # outputs: 12 bytes per minimizer, reserved for a density of 3/(w+1)
-        # (the expected density is about 2/(w+1)); more grows the buffer
-        out_bytes = 12 * max(1 << 16, staging_bytes * 3 // (self.w + 1))
+        # outputs: the per-read offsets and 12 bytes per minimizer, reserved
+        # for the density start() copies back speculatively; more grows the
+        # buffer
+        out_bytes = staging_bytes + 12 * (1024 + 5 * staging_bytes // (2 * (self.w + 1)))
         for si in range(len(self.streams)):
             self._pinned(si, staging_bytes, exact=True)
             self._pinned_out(si, out_bytes, exact=True)
@@ -303,6 +304,20 @@ class GPUExecutor(Executor):
                 p("seqs"), p("offsets"), nreads, nbases, self.k, self.w, self.flags, p("hash"),
                 p("pos"), p("read"), bound, p("read_out"), p("ws"), lay["ws"][1],
                 ctypes.c_void_p(stream.cuda_stream))
+            if st == 0:
+                # queue the copies back behind the kernel: the per-read offsets
+                # and the minimizers up to a density of 2.5/(w+1) (random
+                # sequence: about 2/(w+1)), so that a batch within it needs no
+                # further round trip once its event fires
+                est = min(bound, 1024 + 5 * nbases // (2 * (self.w + 1)))
+                rob = Arena.round(8 * (nreads + 1))
+                out = self._pinned_out(si, rob + 12 * est)
+                out[:8 * (nreads + 1)].copy_(view("read_out", np.int64, nreads + 1),
+                                             non_blocking=True)
+                if est:
+                    out[rob:rob + 8 * est].copy_(view("hash", np.int64, est), non_blocking=True)
+                    out[rob + 8 * est:rob + 12 * est].copy_(view("pos", np.int32, est),
+                                                            non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
         if st != 0:
@@ -310,7 +325,7 @@ class GPUExecutor(Executor):
             _lib.check(st, "sws_minimizers_batch")
         # keep the pinned staging alive until the copies finished
         return {"reqs": reqs, "event": ev, "stream": si, "lay": lay, "slot": slot,
-                "nreads": nreads, "bound": bound}
+                "nreads": nreads, "bound": bound, "est": est, "rob": rob}
 
     def done(self, handle) -> bool:
         return handle["event"].query()
@@ -327,22 +342,30 @@ class GPUExecutor(Executor):
             nb = count * torch.tensor([], dtype=dtype).element_size()
             return self.arena_dev[slot + o: slot + o + nb].view(dtype)
 
-        with torch.cuda.stream(stream):
-            ro = dev("read_out", nreads + 1, torch.int64).cpu().numpy().view(np.uint64)
-            total = int(ro[-1])
-            if total == 0xFFFFFFFFFFFFFFFF or total > handle["bound"]:
-                raise _lib.SwsError(_lib.SWS_ERR_DEVICE, "batch kernel reported an internal error")
-            # through this stream's pinned buffer: a copy to pageable memory
-            # measured several times slower for megabyte outputs
-            out = self._pinned_out(handle["stream"], 12 * total)
-            out[:8 * total].copy_(dev("hash", total, torch.int64).view(torch.uint8),
-                                  non_blocking=True)
-            out[8 * total:12 * total].copy_(dev("pos", total, torch.int32).view(torch.uint8),
-                                            non_blocking=True)
-            stream.synchronize()
-        o = out.numpy()
-        h = o[:8 * total].view(np.uint64)
-        p = o[8 * total:12 * total].view(np.uint32)
+        # the copies queued by start() have finished with the event
+        est, rob = handle["est"], handle["rob"]
+        o = self.out_staging[handle["stream"]].numpy()
+        ro = o[:8 * (nreads + 1)].view(np.uint64)
+        total = int(ro[-1])
+        if total == 0xFFFFFFFFFFFFFFFF or total > handle["bound"]:
+            raise _lib.SwsError(_lib.SWS_ERR_DEVICE, "batch kernel reported an internal error")
+        if total <= est:
+            h = o[rob:rob + 8 * total].view(np.uint64)
+            p = o[rob + 8 * est:rob + 8 * est + 4 * total].view(np.uint32)
+        else:
+            # denser than estimated: copy them all, through the (grown) pinned
+            # buffer; a copy to pageable memory measured several times slower
+            ro = ro.copy()
+            with torch.cuda.stream(stream):
+                out = self._pinned_out(handle["stream"], 12 * total)
+                out[:8 * total].copy_(dev("hash", total, torch.int64).view(torch.uint8),
+                                      non_blocking=True)
+                out[8 * total:12 * total].copy_(dev("pos", total, torch.int32).view(torch.uint8),
+                                                non_blocking=True)
+                stream.synchronize()
+            o = out.numpy()
+            h = o[:8 * total].view(np.uint64)
+            p = o[8 * total:12 * total].view(np.uint32)
         return _split(handle["reqs"], h, p, ro)  # copies out of the pinned buffer
 
 

@@ -73,3 +73,24 @@ def test_poisson_replay_short():
     srv.stop()
     st = latency_stats(srv.completed)
     assert st["n"] == len(reqs) and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_denser_than_the_copy_back_estimate():
+    """A poly-A read stores a minimizer at every window (every k-mer ties,
+    the leftmost wins), far above the density the executor copies back with
+    the kernel; the rest comes by a second copy.  A random read in the same
+    batch and alone stays exact."""
+    torch_cuda()
+    from paper_1811_10074_amd.serve import GPUExecutor, Server
+    dense = np.frombuffer(b"A" * 20000, dtype=np.uint8).copy()
+    rnd = inputs.dna(30000, seed=9, n_rate=0.01)
+    seqs = np.concatenate([dense, rnd])
+    off = np.array([0, dense.size, seqs.size], dtype=np.uint64)
+    ex = GPUExecutor(K, W, arena_bytes=1 << 28, streams=2)
+    srv = Server(ex, K, W).start()
+    got = srv.submit(seqs, off).result(timeout=60)
+    alone = srv.submit(rnd, np.array([0, rnd.size], dtype=np.uint64)).result(timeout=60)
+    srv.stop()
+    check(got, seqs, off)
+    check(alone, rnd, np.array([0, rnd.size], dtype=np.uint64))
+    assert got.read_offsets[1] == 20000 - K - W + 2  # every window of the poly-A read
