@@ -947,25 +947,42 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
         if (gw + total > a.capacity) lim = gw >= a.capacity ? 0u : (uint32_t)(a.capacity - gw);
         const uint32_t pos0 = (uint32_t)K0;  // positions are below 2^32
         const uint32_t tmask = FULL ? 0x7FFFu : 0xFFFFFFFFu;
-        for (uint32_t c = 0; c < lim; c += kStage) {
-            uint32_t j = incl - cnt - c;  // rank - c, mod 2^32
+        if (total <= kStage) {  // one round, the usual case: every rank fits
+            uint32_t j = incl - cnt;
 #pragma unroll
             for (int e = 0; e < kR; ++e) {
                 if ((emit >> e) & 1u) {
-                    if (j < kStage) {
-                        sh[j] = ((uint64_t)m[e].hi << 32) | m[e].lo;
-                        sp[j] = pos0 + (m[e].tag & tmask);
-                    }
+                    sh[j] = ((uint64_t)m[e].hi << 32) | m[e].lo;
+                    sp[j] = pos0 + (m[e].tag & tmask);
                     ++j;
                 }
             }
             wave_lds_sync();
-            const uint32_t nc = min(kStage, lim - c);
-            for (uint32_t r = (uint32_t)lane; r < nc; r += kWave) {
-                a.out_hash[gw + c + r] = sh[r];
-                a.out_pos[gw + c + r] = sp[r];
+            for (uint32_t r = (uint32_t)lane; r < lim; r += kWave) {
+                a.out_hash[gw + r] = sh[r];
+                a.out_pos[gw + r] = sp[r];
             }
-            wave_lds_sync();
+        } else {
+            for (uint32_t c = 0; c < lim; c += kStage) {
+                uint32_t j = incl - cnt - c;  // rank - c, mod 2^32
+#pragma unroll
+                for (int e = 0; e < kR; ++e) {
+                    if ((emit >> e) & 1u) {
+                        if (j < kStage) {
+                            sh[j] = ((uint64_t)m[e].hi << 32) | m[e].lo;
+                            sp[j] = pos0 + (m[e].tag & tmask);
+                        }
+                        ++j;
+                    }
+                }
+                wave_lds_sync();
+                const uint32_t nc = min(kStage, lim - c);
+                for (uint32_t r = (uint32_t)lane; r < nc; r += kWave) {
+                    a.out_hash[gw + c + r] = sh[r];
+                    a.out_pos[gw + c + r] = sp[r];
+                }
+                wave_lds_sync();
+            }
         }
     }
 }
