@@ -808,8 +808,13 @@ __device__ __forceinline__ uint32_t previous_window_bits(uint32_t wbad) {
     return ((wbad << 1) | ((from_prev_lane(wbad) >> 15) & 1u)) & 0xFFFFu;
 }
 
+// From the 2-bit layout the kernel runs 5 waves per SIMD (96 VGPRs, a few
+// spilled: 0.1540 against 0.1571 ms at 64 Mbases); from ASCII, where the
+// decode needs more registers, that measured slower (0.1787 against 0.1720),
+// so it keeps the compiler's choice (101 VGPRs, 4 waves).
 template <int NT, int IN, bool KM64, bool FULL, int FLAGS>
-__global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, MinimizerArgs a) {
+__global__ __launch_bounds__(NT, IN == kIn2bit ? 5 : 1) void minimizer_wave_kernel(GenomeInput in,
+                                                                                   MinimizerArgs a) {
     constexpr int NWV = NT / kWave;
     static_assert(NWV <= kWave, "one lane per wave of the workgroup");
     __shared__ uint32_t s_code[NWV][kWaveWords], s_inv[NWV][kWaveWords];
