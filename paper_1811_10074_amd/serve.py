@@ -203,14 +203,16 @@ class GPUExecutor(Executor):
         self.lib = _lib.load()
 
     def prepare(self, staging_bytes: int):
-        """Before requests arrive: allocate every stream's pinned input
-        staging for the server's largest batch (pinned allocations are slow
-        and stall the device), and run one small copy and fill on every stream
-        (a stream's first use carries a one-time setup cost)."""
-        # outputs: the per-read offsets and 12 bytes per minimizer, reserved
-        # for the density start() copies back speculatively; more grows the
-        # buffer
-        out_bytes = staging_bytes + 12 * (1024 + 5 * staging_bytes // (2 * (self.w + 1)))
+        """Before requests arrive: allocate every stream's pinned input and
+        output staging for the server's largest batch (pinned allocations are
+        slow and stall the device), and run one small batch on every stream
+        (a stream's first use carries a one-time setup cost).  staging_bytes:
+        the batch's bases plus 8 bytes per read offset."""
+        # outputs: the per-read offsets (at most 2^20 + 1 are reserved) and
+        # 12 bytes per minimizer at the density start() copies back
+        # speculatively; more grows the buffer
+        offsets = min(staging_bytes, 8 * ((1 << 20) + 1) + 256)
+        out_bytes = offsets + 12 * (1024 + 5 * staging_bytes // (2 * (self.w + 1)))
         for si in range(len(self.streams)):
             self._pinned(si, staging_bytes, exact=True)
             self._pinned_out(si, out_bytes, exact=True)
