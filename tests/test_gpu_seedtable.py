@@ -11,7 +11,7 @@ from paper_1811_10074_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TILE = 8192  # entries per workgroup tile of the radix passes
+TILE = 4096  # entries per workgroup tile of the radix passes
 
 
 def check(torch, h, p, bits, shift, with_hash=True):
