@@ -214,16 +214,22 @@ def bench_batch(torch, quick):
                          "minimizers": int(runner.read_out[-1].item())}
     del runner
     torch.cuda.empty_cache()
-    # tuned block size per length bucket, every bucket in one HIP graph
+    # tuned block size per length bucket: eager per-bucket launches, then the
+    # same launches captured in one HIP graph
     sub = slice(0, max(off.size // 20, 2))
     soff = off[sub] - off[0]
-    table, timings = tune.tune(seqs[: int(soff[-1])], soff, k, w, reps=3)
+    table, report = tune.tune(seqs[: int(soff[-1])], soff, k, w, reps=3)
     bb = batch.BucketedBatch(seqs, off, k, w, tune_table=table)
+    ms_e, _, _ = time_launches(torch, bb.launch, 5, 2)
     bb.capture()
     ms_g, med_g, _ = time_launches(torch, bb.replay, 5, 2)
+    out["bucketed_eager"] = {"ms": round(ms_e, 3), "Gbases/s": round(total / (ms_e / 1e3) / 1e9, 2)}
     out["bucketed_graph"] = {"ms": round(ms_g, 3), "Gbases/s": round(total / (ms_g / 1e3) / 1e9, 2),
+                             "graph_gain_vs_eager": round(ms_e / ms_g, 3),
                              "tune_table": {str(b): t for b, t in table.items()},
-                             "tune_ms": {kk: round(v, 3) for kk, v in timings.items()}}
+                             "tune_ms": {"%d/%d" % (b, t): round(v, 3)
+                                         for b, r in report.items() for t, v in r["ms"].items()},
+                             "tune_flat": {str(b): r["flat"] for b, r in report.items()}}
     del bb
     torch.cuda.empty_cache()
     # baseline: one library call per read (no batching), on the first reads

@@ -22,8 +22,9 @@
  *     any error status nothing is enqueued and nothing is written.
  *   - SWS_ERR_DEVICE means the launch itself failed (hipGetLastError).
  *     Faults during execution surface at the caller's next synchronization.
- *   - Calls are re-entrant; calls on different streams may overlap as long as
- *     they do not share a workspace or an output buffer.
+ *   - Calls are re-entrant and keep no process-wide state; calls on different
+ *     streams may overlap as long as they do not share a workspace or an
+ *     output buffer.
  *   - Every integer result is exact; there is no floating point anywhere.
  */
 #ifndef SWS_H
@@ -37,8 +38,10 @@ extern "C" {
 #endif
 
 /* 2: seed tables, the prefix-difference and scalar-input paths, SWS_SPLIT_AT_INVALID,
- * SWS_WORKSPACE_KEPT (all additions; no call changed its meaning) */
-#define SWS_ABI_VERSION 2u
+ *    SWS_WORKSPACE_KEPT (all additions; no call changed its meaning).
+ * 3: sws_minimizers_batch_ex takes the workgroup size per call; the process-wide
+ *    sws_set_minimizer_block is gone; sws_set_sliding_waves is per thread. */
+#define SWS_ABI_VERSION 3u
 
 typedef enum {
     SWS_OK = 0,
@@ -241,6 +244,19 @@ int sws_minimizers_batch(const uint8_t *seqs, const uint64_t *d_offsets, uint32_
                          uint64_t capacity, uint64_t *d_read_out_offsets, void *workspace,
                          uint64_t ws_bytes, hipStream_t s);
 
+/*
+ * As sws_minimizers_batch with the threads per workgroup of the launch chosen
+ * by the caller (the autotuner's knob): 64, 128, 256 or 512 (1, 2, 4 or 8
+ * wavefront tiles of 1024 k-mer positions per workgroup), or 0 for the
+ * default (256).  Results do not depend on it.  Any other value:
+ * SWS_ERR_INVALID.
+ */
+int sws_minimizers_batch_ex(const uint8_t *seqs, const uint64_t *d_offsets, uint32_t nreads,
+                            uint64_t total_bases, uint32_t k, uint32_t w, uint32_t flags,
+                            uint64_t *out_hash, uint32_t *out_pos, uint32_t *out_read,
+                            uint64_t capacity, uint64_t *d_read_out_offsets, void *workspace,
+                            uint64_t ws_bytes, uint32_t threads, hipStream_t s);
+
 /* ------------------------------------------------------------------------ */
 /* Seed pointer table and seed position table, Sec. 2.4 and Fig. 1.           */
 /* ------------------------------------------------------------------------ */
@@ -283,20 +299,16 @@ int sws_seed_table(const uint64_t *hash, const uint32_t *pos, uint64_t count, ui
 /* ------------------------------------------------------------------------ */
 
 /*
- * Sets the threads per workgroup used by the minimizer kernels for batches
- * whose mean read length falls in bucket `bucket` (0: < 1 kb, 1: < 16 kb,
- * 2: longer).  threads must be 64, 128, 256 or 512.  Applies to later calls
- * in this process.  Errors: SWS_ERR_INVALID.
- */
-int sws_set_minimizer_block(uint32_t bucket, uint32_t threads);
-
-/*
- * Sets how many wavefronts a generic-path sliding-sum launch aims for.  The
- * input is cut into slabs of 64*R elements (R = 8, 16 or 32 by window and
- * operator) and each wavefront streams ceil(slabs / waves) consecutive slabs,
- * so fewer waves means longer streams per wave.  0 restores the default
- * (32768: 128 per compute unit).  Results do not depend on it.  Applies to
- * later calls in this process.  Errors: SWS_ERR_INVALID (waves > 2^24).
+ * Sets how many wavefronts a generic-path (or streaming prefix-path)
+ * sliding-sum launch aims for.  The input is cut into slabs of 64*R elements
+ * (R = 8, 16 or 32 by window and operator) and each wavefront streams
+ * ceil(slabs / waves) consecutive slabs, so fewer waves means longer streams
+ * per wave.  0 restores the default: 128 waves per compute unit, lowered
+ * (down to 4 per compute unit) so that each wave streams at least 32 (w - 1)
+ * elements and the w - 1 elements it re-reads past its range stay within
+ * 1/32 of its reads.  Results do not depend on it.  The setting belongs to the
+ * calling thread: it applies to that thread's later calls only.
+ * Errors: SWS_ERR_INVALID (waves > 2^24).
  */
 int sws_set_sliding_waves(uint64_t waves);
 

@@ -47,7 +47,8 @@ _SIGNATURES = {
     "sws_minimizers_batch_workspace": (c_int, [c_u64, c_u32, c_u32, c_u32, ctypes.POINTER(c_u64)]),
     "sws_minimizers_batch": (c_int, [c_vp, c_vp, c_u32, c_u64, c_u32, c_u32, c_u32, c_vp, c_vp,
                                      c_vp, c_u64, c_vp, c_vp, c_u64, c_vp]),
-    "sws_set_minimizer_block": (c_int, [c_u32, c_u32]),
+    "sws_minimizers_batch_ex": (c_int, [c_vp, c_vp, c_u32, c_u64, c_u32, c_u32, c_u32, c_vp, c_vp,
+                                        c_vp, c_u64, c_vp, c_vp, c_u64, c_u32, c_vp]),
     "sws_set_sliding_waves": (c_int, [c_u64]),
     "sws_seed_table_workspace": (c_int, [c_u64, c_u32, c_vp]),
     "sws_seed_table": (c_int, [c_vp, c_vp, c_u64, c_u32, c_u32, c_vp, c_vp, c_vp, c_vp, c_u64,

@@ -5,8 +5,9 @@
 * ``BatchRunner``: preallocated device buffers for one batch; ``launch()``
   enqueues, ``result()`` synchronizes and returns views.
 * ``BucketedBatch``: splits a batch into read-length buckets, runs each with
-  the block size the tuner chose for its bucket, and can capture the whole
-  sequence of launches into one HIP graph (``capture()`` / ``replay()``).
+  the block size the tuner chose for its bucket (passed per call, no process
+  state), and can capture the whole sequence of launches into one HIP graph
+  (``capture()`` / ``replay()``).
 
 The arithmetic is entirely in libsws (include/sws.h); this module only packs
 CSR offsets, sizes buffers and issues the calls.
@@ -65,10 +66,11 @@ class BatchRunner:
     """Device buffers for one batch of reads (CSR: seqs + offsets)."""
 
     def __init__(self, seqs, offsets_np: np.ndarray, k: int, w: int, canonical=True, hashed=True,
-                 device="cuda", split=False):
+                 device="cuda", split=False, threads: int = 0):
         torch = _torch()
         off = np.ascontiguousarray(offsets_np, dtype=np.uint64)
         self.k, self.w = k, w
+        self.threads = int(threads)  # workgroup size of the launch; 0: the library default
         self.flags = ((0 if canonical else _lib.KMER_FORWARD) | (0 if hashed else _lib.HASH_IDENTITY)
                       | (_lib.SPLIT_AT_INVALID if split else 0))
         self.nreads = int(off.size - 1)
@@ -92,12 +94,15 @@ class BatchRunner:
         for name in ("offsets", "hash", "pos", "read", "read_out", "workspace"):
             _need_cuda(getattr(self, name), name)
 
-    def launch(self):
-        st = _lib.load().sws_minimizers_batch(
+    def launch(self, threads=None):
+        """Enqueue on the current stream; threads overrides the runner's
+        workgroup size for this call."""
+        t = self.threads if threads is None else int(threads)
+        st = _lib.load().sws_minimizers_batch_ex(
             _ptr(self.seqs), _ptr(self.offsets), self.nreads, self.total, self.k, self.w,
             self.flags, _ptr(self.hash), _ptr(self.pos), _ptr(self.read), self.capacity,
-            _ptr(self.read_out), _ptr(self.workspace), self.workspace.numel(), _stream())
-        check(st, "sws_minimizers_batch")
+            _ptr(self.read_out), _ptr(self.workspace), self.workspace.numel(), t, _stream())
+        check(st, "sws_minimizers_batch_ex")
 
     def result(self):
         """Synchronizes; returns (hash, pos, read, read_offsets) device views."""
@@ -125,10 +130,6 @@ def minimizers_batch(seqs, offsets, k: int, w: int, canonical: bool = True, hash
     r.launch()
     h, p, rd, ro = r.result()
     return h.clone(), p.clone(), rd.clone(), ro.clone()
-
-
-def set_block(bucket: int, threads: int) -> None:
-    check(_lib.load().sws_set_minimizer_block(bucket, threads), "sws_set_minimizer_block")
 
 
 class BucketedBatch:
@@ -160,13 +161,12 @@ class BucketedBatch:
             # gather the bucket's reads (host side, once, outside any timing)
             bseq = seqs_np[np.repeat(self.bucket_of == b, lens)]
             self.runners[b] = BatchRunner(torch.from_numpy(bseq).to(device), boff, k, w,
-                                          canonical, hashed, device=device)
+                                          canonical, hashed, device=device,
+                                          threads=int(self.tune_table.get(b, 0)))
         self.graph = None
 
     def launch(self):
-        for b, r in self.runners.items():
-            if b in self.tune_table:
-                set_block(b, int(self.tune_table[b]))
+        for r in self.runners.values():
             r.launch()
 
     def capture(self):

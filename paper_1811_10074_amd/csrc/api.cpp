@@ -16,21 +16,19 @@ bool known_flags(uint32_t flags, bool windows = true, bool kept = false) {
     return (flags & ~ok) == 0u;
 }
 
-// Threads per workgroup of the minimizer kernels, per read-length bucket.
-uint32_t g_min_block[3] = {256, 256, 256};
-// Wavefronts a generic sliding-sum launch aims for (0: the default).
-constexpr uint64_t kDefaultSlidingWaves = 256ull * 128ull;
-uint64_t g_sliding_waves = 0;
+// Wavefronts a generic sliding-sum launch aims for, per calling thread
+// (0: the default, which depends on w).  Thread-local, so calls from
+// different threads never see each other's setting.
+thread_local uint64_t t_sliding_waves = 0;
 
-uint32_t bucket_of(uint64_t total_bases, uint64_t nreads) {
-    const uint64_t mean = nreads ? total_bases / nreads : total_bases;
-    return mean < 1000 ? 0u : (mean < 16000 ? 1u : 2u);
-}
+// Threads per workgroup of the single-sequence block kernel (32 < w <= 1024).
+constexpr uint32_t kBlockThreads = 256;
+// Threads per workgroup of the batched kernel unless the caller picks one.
+constexpr uint32_t kBatchDefaultThreads = 256;
 
-// Smallest tile (most tiles) over the block sizes the library may use: the
-// workspace bound must hold whatever the tuner picks later.
+// Tiles of a single-sequence call: the same tile width the launch uses.
 uint64_t max_tiles(uint64_t nwin, uint32_t w) {
-    const uint32_t tw = sws::minimizer_windows_per_tile(128, w);
+    const uint32_t tw = sws::minimizer_windows_per_tile(kBlockThreads, w);
     if (tw == 0) return 0;
     return (nwin + tw - 1) / tw;
 }
@@ -62,10 +60,10 @@ int minimizers_common(const sws::GenomeInput& in, uint64_t n, uint32_t k, uint32
     const uint64_t nwin = window_count(n, k, w);
     if (nwin > 0 && (out_hash == nullptr || out_pos == nullptr)) return SWS_ERR_INVALID;
     if (capacity < nwin) return SWS_ERR_CAPACITY;
-    const uint32_t nt = g_min_block[bucket_of(n, 1)];
-    const uint32_t tw = sws::minimizer_windows_per_tile(nt, w);
+    const uint32_t tw = sws::minimizer_windows_per_tile(kBlockThreads, w);
+    if (tw == 0) return SWS_ERR_UNSUPPORTED;  // unreachable for w <= 1024
     const uint64_t ntiles = nwin ? (nwin + tw - 1) / tw : 0;
-    const uint64_t need = sws::minimizer_workspace_bytes(max_tiles(nwin, w));
+    const uint64_t need = sws::minimizer_workspace_bytes(ntiles);
     if (workspace == nullptr || ws_bytes < need || ((uintptr_t)workspace & 7u)) return SWS_ERR_WORKSPACE;
     if (nwin == 0) {
         // nothing to compute; the count is still written on the stream
@@ -83,7 +81,8 @@ int minimizers_common(const sws::GenomeInput& in, uint64_t n, uint32_t k, uint32
     a.out_pos = out_pos;
     a.capacity = capacity;
     a.d_count = d_count;
-    return sws::launch_minimizers(in, a, nt, workspace, s, (flags & SWS_WORKSPACE_KEPT) != 0u) == 0
+    return sws::launch_minimizers(in, a, kBlockThreads, workspace, s,
+                                  (flags & SWS_WORKSPACE_KEPT) != 0u) == 0
                ? SWS_OK
                : SWS_ERR_DEVICE;
 }
@@ -141,7 +140,7 @@ int sws_sliding_sum_ex(int op, uint64_t w, const void* x, uint64_t n, void* y, i
                    : SWS_ERR_DEVICE;
     }
     if (w > sws::generic_max_window()) return SWS_ERR_UNSUPPORTED;
-    const uint64_t waves = g_sliding_waves ? g_sliding_waves : kDefaultSlidingWaves;
+    const uint64_t waves = t_sliding_waves;  // 0: the launcher's default for (n, w)
     const int rc = use == SWS_PATH_PREFIX
                        ? sws::launch_sliding_prefix(op, x, n, (uint32_t)w, y, count, waves, s)
                        : sws::launch_sliding_generic(op, x, n, (uint32_t)w, y, count, waves, s);
@@ -237,13 +236,15 @@ int sws_minimizers_batch_workspace(uint64_t total_bases, uint32_t nreads, uint32
     return SWS_OK;
 }
 
-int sws_minimizers_batch(const uint8_t* seqs, const uint64_t* d_offsets, uint32_t nreads,
-                         uint64_t total_bases, uint32_t k, uint32_t w, uint32_t flags,
-                         uint64_t* out_hash, uint32_t* out_pos, uint32_t* out_read,
-                         uint64_t capacity, uint64_t* d_read_out_offsets, void* workspace,
-                         uint64_t ws_bytes, hipStream_t s) {
+int sws_minimizers_batch_ex(const uint8_t* seqs, const uint64_t* d_offsets, uint32_t nreads,
+                            uint64_t total_bases, uint32_t k, uint32_t w, uint32_t flags,
+                            uint64_t* out_hash, uint32_t* out_pos, uint32_t* out_read,
+                            uint64_t capacity, uint64_t* d_read_out_offsets, void* workspace,
+                            uint64_t ws_bytes, uint32_t threads, hipStream_t s) {
     const int st = check_batch_args(total_bases, k, w, flags);
     if (st != SWS_OK) return st;
+    if (threads == 0) threads = kBatchDefaultThreads;
+    if (threads != 64 && threads != 128 && threads != 256 && threads != 512) return SWS_ERR_INVALID;
     if (d_offsets == nullptr || d_read_out_offsets == nullptr) return SWS_ERR_INVALID;
     if (total_bases > 0 && seqs == nullptr) return SWS_ERR_INVALID;
     if (capacity > 0 && (out_hash == nullptr || out_pos == nullptr || out_read == nullptr))
@@ -277,9 +278,18 @@ int sws_minimizers_batch(const uint8_t* seqs, const uint64_t* d_offsets, uint32_
     a.out_read = out_read;
     a.capacity = capacity;
     a.read_out = d_read_out_offsets;
-    const uint32_t nt = g_min_block[bucket_of(total_bases, nreads)];
-    return sws::launch_minimizers_batch(in, a, nt > 256 ? 256 : nt, workspace, s) == 0
-               ? SWS_OK : SWS_ERR_DEVICE;
+    return sws::launch_minimizers_batch(in, a, threads, workspace, s) == 0 ? SWS_OK
+                                                                          : SWS_ERR_DEVICE;
+}
+
+int sws_minimizers_batch(const uint8_t* seqs, const uint64_t* d_offsets, uint32_t nreads,
+                         uint64_t total_bases, uint32_t k, uint32_t w, uint32_t flags,
+                         uint64_t* out_hash, uint32_t* out_pos, uint32_t* out_read,
+                         uint64_t capacity, uint64_t* d_read_out_offsets, void* workspace,
+                         uint64_t ws_bytes, hipStream_t s) {
+    return sws_minimizers_batch_ex(seqs, d_offsets, nreads, total_bases, k, w, flags, out_hash,
+                                   out_pos, out_read, capacity, d_read_out_offsets, workspace,
+                                   ws_bytes, 0, s);
 }
 
 int sws_seed_table_workspace(uint64_t count, uint32_t bits, uint64_t* bytes) {
@@ -307,14 +317,7 @@ int sws_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count, ui
 
 int sws_set_sliding_waves(uint64_t waves) {
     if (waves > (1ull << 24)) return SWS_ERR_INVALID;
-    g_sliding_waves = waves;
-    return SWS_OK;
-}
-
-int sws_set_minimizer_block(uint32_t bucket, uint32_t threads) {
-    if (bucket > 2 || (threads != 64 && threads != 128 && threads != 256 && threads != 512))
-        return SWS_ERR_INVALID;
-    g_min_block[bucket] = threads;
+    t_sliding_waves = waves;
     return SWS_OK;
 }
 

@@ -1426,15 +1426,11 @@ int launch_minimizers(const GenomeInput& in, MinimizerArgs a, uint32_t nt, void*
         else launch_min_wave<NT, kIn2bit>(in, a, km64, full, s);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
-    if (in.kind == kInAscii) {
-        if (nt == 128) launch_min_nt<128, kInAscii>(in, a, km64, full, s);
-        else if (nt == 512) launch_min_nt<512, kInAscii>(in, a, km64, full, s);
-        else launch_min_nt<256, kInAscii>(in, a, km64, full, s);
-    } else {
-        if (nt == 128) launch_min_nt<128, kIn2bit>(in, a, km64, full, s);
-        else if (nt == 512) launch_min_nt<512, kIn2bit>(in, a, km64, full, s);
-        else launch_min_nt<256, kIn2bit>(in, a, km64, full, s);
-    }
+    // the block kernel is built for 256-thread tiles only; a.tw was computed
+    // for that width
+    if (nt != 256) return -1;
+    if (in.kind == kInAscii) launch_min_nt<256, kInAscii>(in, a, km64, full, s);
+    else launch_min_nt<256, kIn2bit>(in, a, km64, full, s);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

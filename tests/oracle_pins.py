@@ -2,7 +2,8 @@
 
 Every check takes a loaded oracle library (``oracle.load()`` or a deliberately
 mutated build) and raises AssertionError on a mismatch.  The facts come from
-the paper (Eq. 2, Alg. 1, Alg. 2, the Fig. 2 worked example), from closed forms
+the paper (Eq. 2, the scalar- and vector-input forms of Sec. 3.1, the Fig. 2
+worked example), from closed forms
 (prefix differences for +, global extrema, products), from library routines
 (numpy's sliding-window views), from mathematics (the hash constants), and from
 brute force on tiny inputs.  ``ALL_PINS`` lists them so that a test can show
@@ -37,67 +38,72 @@ def _from_list(op, ys):
     return np.array(ys, dtype=np.uint32)
 
 
-def alg1_scalar_input(op, w, xs, P):
-    """Alg. 1 (Scalar Input): a P-lane state Y holding the running suffix sums
-    of the last w-1 elements; each new element is broadcast to lanes 0..w-1,
-    lane 0 then holds the next output and Y shifts one lane left.  P > w."""
+def _fold(f, vals):
+    acc = vals[0]
+    for v in vals[1:]:
+        acc = f(acc, v)
+    return acc
+
+
+def carried_state(op, w, xs, i):
+    """The state Sec. 3.1 carries from one input to the next: before x_i
+    arrives, entry t (t = 0 .. w-2) holds x_{i-w+1+t} (+) ... (+) x_{i-1}, the
+    part of each pending window already seen (the identity where it reaches
+    before x_0)."""
     f, e = brute.op_fn(op), IDENT[op]
+    return [_fold(f, [e] + xs[max(0, i - w + 1 + t):i]) for t in range(w - 1)]
+
+
+def scalar_input_outputs(op, w, xs):
+    """The scalar-input form of Sec. 3.1 restated as a state machine: one
+    input at a time, the window that ends at x_i is entry 0 of the state
+    combined with x_i, and every pending partial window takes x_i on its
+    right.  The state is checked against its definition at every step."""
+    f = brute.op_fn(op)
     n = len(xs)
     if n < w:
         return []
-    Y = [e] * P
-    for t in range(w - 1):           # Y[t] = x_t (+) ... (+) x_{w-2}
-        acc = xs[t]
-        for j in range(t + 1, w - 1):
-            acc = f(acc, xs[j])
-        Y[t] = acc
+    state = carried_state(op, w, xs, w - 1)
     out = []
     for i in range(w - 1, n):
-        X = [xs[i]] * w + [e] * (P - w)
-        Y = [f(Y[t], X[t]) for t in range(P)]   # earlier elements on the left
-        out.append(Y[0])
-        Y = Y[1:] + [e]
+        assert state == carried_state(op, w, xs, i), ("state", op, w, i)
+        out.append(f(state[0], xs[i]) if w > 1 else xs[i])
+        # windows still pending after x_i: those ending at x_{i+1} .. x_{i+w-1}
+        state = [f(v, xs[i]) for v in state[1:]] + ([xs[i]] if w > 1 else [])
     return out
 
 
-def alg2_vector_input(op, w, xs, P):
-    """Alg. 2 (Vector Input), P >= w, with the off-by-one reading of Y1: the
-    state carried to the next vector is the suffix sums of the last w-1
-    elements, X_{P-w+1+t} (+) ... (+) X_{P-1}, t = 0..w-2.  The blocks start
-    at i = w-1, w-1+P, ...; the tail is padded with the identity and outputs
-    past n-w are dropped."""
+def block_input_outputs(op, w, xs, P):
+    """The vector-input form of Sec. 3.1 restated by splitting each window at
+    a block boundary: blocks of P >= w inputs start at w-1, w-1+P, ...; the
+    window ending at x_j in the block that starts at b is the carried part
+    before b (the state entry for that window) followed by the in-block prefix
+    x_b .. x_j, or lies wholly inside the block.  The state passed on is the
+    definition of carried_state at the next block start."""
     f, e = brute.op_fn(op), IDENT[op]
     n = len(xs)
     if n < w:
         return []
-    Y = [e] * P
-    for t in range(w - 1):
-        acc = xs[t]
-        for j in range(t + 1, w - 1):
-            acc = f(acc, xs[j])
-        Y[t] = acc
     out = [None] * (n - w + 1)
-    i = w - 1
-    while i < n:
-        X = [xs[i + j] if i + j < n else e for j in range(P)]
-        X1 = []
-        for j in range(P):               # prefix sums, then windows of w addends
-            acc = X[max(0, j - w + 1)]
-            for q in range(max(0, j - w + 1) + 1, j + 1):
-                acc = f(acc, X[q])
-            X1.append(acc)
-        Y1 = [e] * P
-        for t in range(w - 1):           # suffix sums of the last w-1 elements
-            acc = X[P - w + 1 + t]
-            for q in range(P - w + 2 + t, P):
-                acc = f(acc, X[q])
-            Y1[t] = acc
-        for j in range(P):
-            o = i - w + 1 + j
-            if o <= n - w:
-                out[o] = f(Y[j], X1[j])
-        Y = Y1
-        i += P
+    b = w - 1
+    state = carried_state(op, w, xs, b)
+    while b < n:
+        blk = [xs[j] if j < n else e for j in range(b, b + P)]
+        pref = []
+        for v in blk:                     # in-block prefixes x_b .. x_j
+            pref.append(v if not pref else f(pref[-1], v))
+        for q in range(P):
+            j = b + q
+            if j >= n:
+                break
+            start = j - w + 1
+            if start < b:                 # spans the block start
+                y = f(state[q], pref[q]) if w > 1 else pref[q]
+            else:                         # wholly inside the block
+                y = _fold(f, blk[start - b:q + 1])
+            out[start] = y
+        b += P
+        state = carried_state(op, w, xs, b)
     return out
 
 
@@ -237,7 +243,10 @@ def pin_affine_reductions(lib):
 
 
 def pin_paper_algorithms(lib):
-    """Alg. 1 and Alg. 2 of Sec. 3.1 give the oracle's outputs, every op."""
+    """The two vector forms of Sec. 3.1, restated from the windows they
+    combine: one input at a time through the carried state of partial
+    windows, and one block of P >= w inputs at a time by splitting windows at
+    the block start.  Both give the oracle's outputs, every op."""
     rng = np.random.default_rng(16)
     for op in ("add", "min", "max", "affine"):
         for n in (1, 5, 23, 64):
@@ -249,14 +258,11 @@ def pin_paper_algorithms(lib):
             xs = _to_list(op, x)
             for w in (1, 2, 3, 5, 8):
                 exp = oracle.sliding_sum(op, w, x, lib=lib)
-                for P in (w + 1, w + 3, 16):
-                    if P <= w:
-                        continue
-                    assert np.array_equal(_from_list(op, alg1_scalar_input(op, w, xs, P)), exp), (op, n, w, P)
+                assert np.array_equal(_from_list(op, scalar_input_outputs(op, w, xs)), exp), (op, n, w)
                 for P in (w, w + 2, 16):
                     if P < w:
                         continue
-                    assert np.array_equal(_from_list(op, alg2_vector_input(op, w, xs, P)), exp), (op, n, w, P)
+                    assert np.array_equal(_from_list(op, block_input_outputs(op, w, xs, P)), exp), (op, n, w, P)
 
 
 # ---------------------------------------------------------------- hash pins

@@ -25,7 +25,7 @@ def test_exports_every_header_function(lib):
 
 
 def test_version_and_status(lib):
-    assert lib.sws_abi_version() == 2
+    assert lib.sws_abi_version() == 3
     for st in (0, -1, -2, -3, -4, -5):
         assert lib.sws_status_str(st)
     assert b"unknown" in lib.sws_status_str(7)
@@ -79,8 +79,11 @@ def test_minimizer_validation(lib):
     assert lib.sws_minimizers(NULL, n, 15, 10, 0, FAKE, FAKE, bound, FAKE, FAKE, 1 << 20, s) == _lib.SWS_ERR_INVALID
     assert lib.sws_minimizers(FAKE, 1 << 32, 15, 10, 0, FAKE, FAKE, 1 << 33, FAKE, FAKE, 1 << 30, s) == _lib.SWS_ERR_UNSUPPORTED
     assert lib.sws_minimizers_2bit(ctypes.c_void_p(0x10002), NULL, n, 15, 10, 0, FAKE, FAKE, bound, FAKE, FAKE, 1 << 20, s) == _lib.SWS_ERR_INVALID
-    assert lib.sws_set_minimizer_block(0, 100) == _lib.SWS_ERR_INVALID
-    assert lib.sws_set_minimizer_block(3, 256) == _lib.SWS_ERR_INVALID
+    # the batched call's workgroup size is an argument: 0 (default) or 64..512
+    for bad in (1, 100, 1024):
+        assert lib.sws_minimizers_batch_ex(FAKE, FAKE, 10, 1000, 15, 10, 0, FAKE, FAKE, FAKE,
+                                           1 << 20, FAKE, FAKE, 1 << 30, bad, s) == _lib.SWS_ERR_INVALID
+    assert not hasattr(lib, "sws_set_minimizer_block")
     assert lib.sws_set_sliding_waves((1 << 24) + 1) == _lib.SWS_ERR_INVALID
     # split semantics: minimizers only, w <= 32
     b2 = ctypes.c_uint64(0)

@@ -95,8 +95,9 @@ def test_config4_subsample_bucketed_graph():
     torch = torch_cuda()
     from paper_1811_10074_amd import batch, tune
     seqs, off = inputs.read_batch(n_short=20_000, n_long=300, seed=3)
-    table, timings = tune.tune(seqs, off, 15, 10, reps=2)
+    table, report = tune.tune(seqs, off, 15, 10, reps=2)
     assert set(table) <= {0, 1, 2} and all(t in tune.CANDIDATES for t in table.values())
+    assert set(report) == set(table)
     bb = batch.BucketedBatch(seqs, off, 15, 10, tune_table=table)
     bb.capture()
     eh, ep, er, ero = oracle.minimizers_batch(seqs, off, 15, 10)
@@ -162,3 +163,23 @@ def test_truncated_capacity():
         assert np.array_equal(host_u32(r.read[:cap]), er[:cap]), cap
         assert bool((r.hash[cap:] == -5).all()) and bool((r.pos[cap:] == -5).all()), cap
         assert bool((r.read[cap:] == -5).all()), cap
+
+
+@pytest.mark.parametrize("threads", [0, 64, 128, 256, 512])
+def test_block_sizes(threads):
+    """Every workgroup size the batched call accepts (the tuner's candidates)
+    gives the oracle's output: short and long reads, empty reads, N bases."""
+    torch = torch_cuda()
+    from paper_1811_10074_amd import batch
+    rng = np.random.default_rng(threads + 1)
+    lens = np.concatenate([rng.integers(0, 400, 600), rng.integers(1000, 30000, 12), [0, 0, 5]])
+    rng.shuffle(lens)
+    seqs, off = make_batch(lens, seed=threads + 3)
+    for k, w in ((15, 10), (21, 28), (31, 18)):
+        r = batch.BatchRunner(torch.from_numpy(seqs).cuda(), off, k, w, threads=threads)
+        r.launch()
+        h, p, rd, ro = r.result()
+        eh, ep, er, ero = oracle.minimizers_batch(seqs, off, k, w)
+        assert np.array_equal(ro.cpu().numpy().view(np.uint64), ero), (threads, k, w)
+        assert np.array_equal(host_u32(rd), er) and np.array_equal(host_u32(p), ep), (threads, k, w)
+        assert np.array_equal(host_u64(h), eh), (threads, k, w)

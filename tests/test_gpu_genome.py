@@ -122,6 +122,24 @@ def test_minimizers_random(k, w):
             assert_same_minimizers(torch, s, k, w, can, hsh, tag="flags")
 
 
+@pytest.mark.parametrize("w", [33, 64, 500, 992, 993, 1000, 1024])
+def test_block_kernel_workspace_sizes(w):
+    """Windows above 32 run on the 256-thread block kernel: the workspace the
+    query returns holds every tile of the launch (regression: the query and the
+    launch once assumed different tile widths), from one tile to many."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    for n in (16_000, 20_481, 150_001):
+        s = inputs.dna(n, seed=n + w, n_rate=0.01)
+        need = sws.minimizer_workspace_bytes(n, 13, w)
+        r = sws.MinimizerRunner(n, 13, w)
+        assert r.workspace.numel() == max(need, 8)
+        r.launch(seq=seq_dev(torch, s))
+        h, p = r.result()
+        eh, ep = oracle.minimizers(s, 13, w)
+        assert np.array_equal(host_u32(p), ep) and np.array_equal(host_u64(h), eh), (n, w)
+
+
 def test_minimizers_structured():
     """Repeats and ties (poly-A hashes to 0; tandem repeats tie the hash) and
     long N runs that empty whole windows and tiles."""
