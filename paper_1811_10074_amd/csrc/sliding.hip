@@ -825,7 +825,6 @@ int launch_sliding_scalar(int op, const void* x, uint64_t n, uint32_t w, void* y
 // Launchers.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kDefaultSlidingWaves = 256ull * 128ull;  // 128 per compute unit
-constexpr uint64_t kMinSlidingWaves = 256ull * 4ull;        // 4 per compute unit
 
 template <class Op, int R, int WAVES, bool PFX = false>
 static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
@@ -833,19 +832,8 @@ static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64
     using T = typename Op::T;
     constexpr uint64_t S = kWave * R;
     const uint64_t total_slabs = (count + S - 1) / S;
-    uint64_t spw;
-    if (target_waves) {
-        spw = (total_slabs + target_waves - 1) / target_waves;
-    } else {
-        // 128 waves per compute unit, each streaming enough slabs that the
-        // w - 1 halo it re-reads from the next wave's range stays within 1/32
-        // of its reads, as long as at least 4 waves per compute unit remain
-        spw = (total_slabs + kDefaultSlidingWaves - 1) / kDefaultSlidingWaves;
-        const uint64_t halo_spw = (32ull * (w - 1u) + S - 1) / S;
-        const uint64_t fill_spw = (total_slabs + kMinSlidingWaves - 1) / kMinSlidingWaves;
-        const uint64_t want = halo_spw < fill_spw ? halo_spw : fill_spw;
-        if (spw < want) spw = want;
-    }
+    const uint64_t tw = target_waves ? target_waves : kDefaultSlidingWaves;
+    uint64_t spw = (total_slabs + tw - 1) / tw;
     if (spw < 1) spw = 1;
     const uint64_t waves = (total_slabs + spw - 1) / spw;
     const uint64_t blocks = (waves + WAVES - 1) / WAVES;

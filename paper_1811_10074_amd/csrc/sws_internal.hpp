@@ -13,8 +13,7 @@ enum { kOpAdd = 0, kOpMin = 1, kOpMax = 2, kOpAffine = 3 };
 uint32_t generic_max_window();
 uint32_t log_max_window();
 // target_waves: wavefronts the launch aims for; each streams
-// ceil(slabs / target_waves) consecutive slabs (0: a default that grows the
-// slabs per wave with w, so the re-read halo stays small).
+// ceil(slabs / target_waves) consecutive slabs (0: the default, 32768).
 int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
                            uint64_t target_waves, hipStream_t s);
 uint32_t scalar_max_window();
