@@ -16,15 +16,16 @@
  * Conventions for every entry point:
  *   - Data pointers are device pointers owned by the caller.  The library
  *     never allocates, frees or synchronizes; every byte of scratch comes from
- *     the caller's workspace; all work is enqueued on the given stream, so the
+ *     the caller's workspace (sws_minimizers_noalloc alone uses a static
+ *     device array instead); all work is enqueued on the given stream, so the
  *     calls may be captured into a HIP graph.
  *   - Arguments are validated on the host before anything is enqueued.  On
  *     any error status nothing is enqueued and nothing is written.
  *   - SWS_ERR_DEVICE means the launch itself failed (hipGetLastError).
  *     Faults during execution surface at the caller's next synchronization.
- *   - Calls are re-entrant and keep no process-wide state; calls on different
- *     streams may overlap as long as they do not share a workspace or an
- *     output buffer.
+ *   - Calls are re-entrant and keep no process-wide state (except
+ *     sws_minimizers_noalloc's scratch array); calls on different streams may
+ *     overlap as long as they do not share a workspace or an output buffer.
  *   - Every integer result is exact; there is no floating point anywhere.
  */
 #ifndef SWS_H
@@ -213,6 +214,35 @@ int sws_minimizers_2bit(const uint32_t *packed, const uint32_t *invalid, uint64_
                         uint32_t w, uint32_t flags, uint64_t *out_hash, uint32_t *out_pos,
                         uint64_t capacity, uint64_t *d_count, void *workspace, uint64_t ws_bytes,
                         hipStream_t s);
+
+/*
+ * sws_minimizers without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The call allocates nothing and calls no
+ * allocating routine; its look-back scratch is a static device array of
+ * SWS_NOALLOC_SCRATCH_BYTES bytes inside the library, one per GPU, held from
+ * the first call on that GPU until the process ends.
+ *   Arguments and results: as sws_minimizers (ASCII input).
+ *   flags     : SWS_KMER_* | SWS_HASH_* | SWS_SPLIT_AT_INVALID; the scratch is
+ *               cleared on every call (one small kernel), so SWS_WORKSPACE_KEPT
+ *               is SWS_ERR_INVALID.
+ *   s         : a stream of the calling thread's current device (the null
+ *               stream included); a stream of another device is
+ *               SWS_ERR_INVALID.
+ * Limit: the request must fit the array, i.e. sws_minimizers_workspace(n, k, w)
+ * <= SWS_NOALLOC_SCRATCH_BYTES (256 bytes plus 64 per look-back participant:
+ * about 2.6e8 bases at w <= 32, about 2.6e8 windows above); a larger request
+ * is SWS_ERR_WORKSPACE and enqueues nothing.
+ * Concurrency: every call on one GPU uses that GPU's one array, so calls that
+ * overlap on one GPU (other streams, other threads) race and their results
+ * are undefined; serialize them, or use sws_minimizers with a workspace each.
+ * Errors: as sws_minimizers, plus SWS_ERR_DEVICE when the array's address
+ * cannot be obtained.
+ */
+#define SWS_NOALLOC_SCRATCH_BYTES (4u << 20)
+int sws_minimizers_noalloc(const uint8_t *seq, uint64_t n, uint32_t k, uint32_t w, uint32_t flags,
+                           uint64_t *out_hash, uint32_t *out_pos, uint64_t capacity,
+                           uint64_t *d_count, hipStream_t s);
 
 /* ------------------------------------------------------------------------ */
 /* Batched minimizers over many reads in one launch.                          */

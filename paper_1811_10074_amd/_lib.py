@@ -19,6 +19,7 @@ SWS_ERR_CAPACITY = -2
 SWS_ERR_WORKSPACE = -3
 SWS_ERR_DEVICE = -4
 SWS_ERR_UNSUPPORTED = -5
+NOALLOC_SCRATCH_BYTES = 4 << 20  # SWS_NOALLOC_SCRATCH_BYTES
 
 OPS = {"add": 0, "min": 1, "max": 2, "affine": 3}
 PATHS = {"auto": 0, "generic": 1, "log": 2, "prefix": 3, "scalar": 4}
@@ -44,6 +45,8 @@ _SIGNATURES = {
                                c_u64, c_vp]),
     "sws_minimizers_2bit": (c_int, [c_vp, c_vp, c_u64, c_u32, c_u32, c_u32, c_vp, c_vp, c_u64,
                                     c_vp, c_vp, c_u64, c_vp]),
+    "sws_minimizers_noalloc": (c_int, [c_vp, c_u64, c_u32, c_u32, c_u32, c_vp, c_vp, c_u64, c_vp,
+                                       c_vp]),
     "sws_minimizers_batch_workspace": (c_int, [c_u64, c_u32, c_u32, c_u32, ctypes.POINTER(c_u64)]),
     "sws_minimizers_batch": (c_int, [c_vp, c_vp, c_u32, c_u64, c_u32, c_u32, c_u32, c_vp, c_vp,
                                      c_vp, c_u64, c_vp, c_vp, c_u64, c_vp]),

@@ -51,15 +51,25 @@ uint64_t window_count(uint64_t n, uint32_t k, uint32_t w) {
     return n >= need ? n - need + 1 : 0;
 }
 
-int minimizers_common(const sws::GenomeInput& in, uint64_t n, uint32_t k, uint32_t w,
-                      uint32_t flags, uint64_t* out_hash, uint32_t* out_pos, uint64_t capacity,
-                      uint64_t* d_count, void* workspace, uint64_t ws_bytes, hipStream_t s) {
-    int st = check_minimizer_args(n, k, w, flags);
+// Everything a minimizer call checks before it looks at its workspace.
+int check_minimizer_call(uint64_t n, uint32_t k, uint32_t w, uint32_t flags,
+                         const uint64_t* out_hash, const uint32_t* out_pos, uint64_t capacity,
+                         const uint64_t* d_count) {
+    const int st = check_minimizer_args(n, k, w, flags);
     if (st != SWS_OK) return st;
     if (d_count == nullptr) return SWS_ERR_INVALID;
     const uint64_t nwin = window_count(n, k, w);
     if (nwin > 0 && (out_hash == nullptr || out_pos == nullptr)) return SWS_ERR_INVALID;
     if (capacity < nwin) return SWS_ERR_CAPACITY;
+    return SWS_OK;
+}
+
+int minimizers_common(const sws::GenomeInput& in, uint64_t n, uint32_t k, uint32_t w,
+                      uint32_t flags, uint64_t* out_hash, uint32_t* out_pos, uint64_t capacity,
+                      uint64_t* d_count, void* workspace, uint64_t ws_bytes, hipStream_t s) {
+    const int st = check_minimizer_call(n, k, w, flags, out_hash, out_pos, capacity, d_count);
+    if (st != SWS_OK) return st;
+    const uint64_t nwin = window_count(n, k, w);
     const uint32_t tw = sws::minimizer_windows_per_tile(kBlockThreads, w);
     if (tw == 0) return SWS_ERR_UNSUPPORTED;  // unreachable for w <= 1024
     const uint64_t ntiles = nwin ? (nwin + tw - 1) / tw : 0;
@@ -210,6 +220,39 @@ int sws_minimizers_2bit(const uint32_t* packed, const uint32_t* invalid, uint64_
     in.n = n;
     return minimizers_common(in, n, k, w, flags, out_hash, out_pos, capacity, d_count, workspace,
                              ws_bytes, s);
+}
+
+int sws_minimizers_noalloc(const uint8_t* seq, uint64_t n, uint32_t k, uint32_t w, uint32_t flags,
+                           uint64_t* out_hash, uint32_t* out_pos, uint64_t capacity,
+                           uint64_t* d_count, hipStream_t s) {
+    if (n > 0 && seq == nullptr) return SWS_ERR_INVALID;
+    // the scratch is always cleared: whatever another call left there is no
+    // state this call may rely on
+    if (flags & SWS_WORKSPACE_KEPT) return SWS_ERR_INVALID;
+    const int st = check_minimizer_call(n, k, w, flags, out_hash, out_pos, capacity, d_count);
+    if (st != SWS_OK) return st;
+    static_assert(sws::kNoAllocScratchBytes == SWS_NOALLOC_SCRATCH_BYTES, "scratch size");
+    if (sws::minimizer_workspace_bytes(max_tiles(window_count(n, k, w), w)) >
+        sws::kNoAllocScratchBytes)
+        return SWS_ERR_WORKSPACE;
+    // the scratch address belongs to one device: the stream's must be current
+    int cur = -1;
+    hipDevice_t sdev = -1;
+    if (hipGetDevice(&cur) != hipSuccess || hipStreamGetDevice(s, &sdev) != hipSuccess) {
+        (void)hipGetLastError();
+        return SWS_ERR_DEVICE;
+    }
+    if ((int)sdev != cur) return SWS_ERR_INVALID;
+    void* scratch = sws::noalloc_scratch(cur);
+    if (scratch == nullptr) return SWS_ERR_DEVICE;
+    sws::GenomeInput in;
+    memset(&in, 0, sizeof(in));
+    in.kind = sws::kInAscii;
+    in.aligned = ((uintptr_t)seq & 15u) == 0;
+    in.seq = seq;
+    in.n = n;
+    return minimizers_common(in, n, k, w, flags, out_hash, out_pos, capacity, d_count, scratch,
+                             sws::kNoAllocScratchBytes, s);
 }
 
 // Batched calls need w <= 32 (one wavefront's tile) and k + w <= 49 (the

@@ -31,6 +31,8 @@
 #include "sws_internal.hpp"
 #include "sws_scan.hpp"
 
+#include <mutex>
+
 namespace sws {
 
 constexpr int kR = 16;                    // positions per lane
@@ -1368,6 +1370,38 @@ uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t w) {
 
 uint64_t minimizer_workspace_bytes(uint64_t ntiles) {
     return kWsStatusOffset + 8ull * kStatusStride * ntiles;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free minimizer entry point: the look-back header
+// and status words live in this file-scope array instead of a caller
+// workspace.  Each GPU holds its own copy, at its own address, until the
+// process ends; host code must never pass the array's name to a kernel (on
+// the host it is a stand-in, not a device address), only the address
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices];  // per device, filled on first use
+}  // namespace
+
+void* noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[device] == nullptr) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != device) return nullptr;
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();  // leave no sticky error behind for the caller
+            return nullptr;
+        }
+        g_scratch_addr[device] = p;
+    }
+    return g_scratch_addr[device];
 }
 
 template <int NT, int IN, bool KM64, bool FULL>

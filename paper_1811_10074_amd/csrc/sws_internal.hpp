@@ -84,6 +84,11 @@ uint32_t minimizer_tile_windows(uint32_t nt, uint32_t w);
 uint32_t minimizer_wave_max_window();  // largest w of the wave-tile kernels
 uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t w);
 uint64_t minimizer_workspace_bytes(uint64_t ntiles);
+// The allocation-free minimizer call's scratch: a static device array of this
+// many bytes.  noalloc_scratch(device) is its address on `device`, which must
+// be the calling thread's current device (nullptr otherwise or on failure).
+constexpr uint64_t kNoAllocScratchBytes = 4ull << 20;
+void* noalloc_scratch(int device);
 
 // Seed pointer/position tables (seedtable.hip).
 uint64_t seed_table_workspace_bytes(uint64_t count, uint32_t bits);
