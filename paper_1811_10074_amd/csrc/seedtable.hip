@@ -14,17 +14,19 @@
 // wanted in the output (the key is recomputed from the hash), else as
 // (key, pos).  A pass is three launches:
 //   1. digit histogram of each 4096-entry tile (LDS counters per wave; a
-//      digit's run in the scatter is ~16 entries long, and the tile's 54 KB of
-//      LDS staging lets two workgroups share a CU: 0.478 against 0.494 ms for
-//      8192-entry tiles, one workgroup per CU);
+//      digit's run in the scatter is ~16 entries long, and the tile's LDS
+//      staging -- 48 KB with hashes, 32 KB without, plus 10 KB of counters --
+//      lets two workgroups share a CU: 0.478 against 0.494 ms for 8192-entry
+//      tiles, one workgroup per CU);
 //   2. per digit, an exclusive scan over the tiles (one workgroup per digit),
 //      giving every (digit, tile) its offset inside the digit's range;
 //   3. stable scatter: a tile's entries are ranked within their digit in
 //      index order -- per wave, 64 consecutive entries at a time, with the
 //      lanes of equal digit found by 8 ballots -- placed in LDS in digit
 //      order, and written out as runs of consecutive addresses per digit.
-// The pointer table is then the merge of the keys 0 .. 2^bits with the sorted
-// keys (every key's lower bound), cut by merge path into equal shares.
+// The last pass also writes the pointer table (see SeedPtrOut): its input is
+// sorted by the key bits below its digit, which lets each tile own a range of
+// pointer entries and fill it from the run of each digit in its LDS stage.
 #include "sws_device.hpp"
 #include "sws_internal.hpp"
 
@@ -37,14 +39,14 @@ constexpr int kSeedWaves = kSeedNT / kWave;
 constexpr int kSeedRounds = 8;                         // 64-entry rounds per wave
 constexpr uint32_t kSeedTile = kSeedNT * kSeedRounds;  // entries per tile
 constexpr int kDigits = 256;
-constexpr uint32_t kPtrChunk = 4096;                   // pointer entries per workgroup
+constexpr int kXcds = 8;                               // gfx950: 8 accelerator dies
 
 __device__ __forceinline__ uint32_t seed_key(uint64_t h, uint32_t shift, uint32_t mask) {
     return (uint32_t)(h >> shift) & mask;
 }
 
 // Entry of wave wv's share of tile b, round r: tile entries are taken in
-// index order, 1024 per wave, 64 per round.
+// index order, 512 per wave, 64 per round.
 __device__ __forceinline__ uint32_t tile_slot(int wv, int r, int lane) {
     return (uint32_t)wv * (kSeedRounds * kWave) + (uint32_t)r * kWave + (uint32_t)lane;
 }
@@ -184,11 +186,35 @@ __device__ __forceinline__ uint32_t wave_scan256(uint32_t* a, int lane) {
     return run;
 }
 
-// 3. stable scatter of one tile
+// The key of input entry i of a pass.
 template <bool FIRST, bool HASH>
+__device__ __forceinline__ uint32_t seed_in_key(const SeedBuffers& io, uint64_t i, uint32_t shift,
+                                                uint32_t mask) {
+    return (HASH || FIRST) ? seed_key(io.hash_in[i], shift, mask) : io.key_in[i];
+}
+
+// Where the pointer table comes from (the last pass, LAST).  That pass's input
+// is sorted by the key's low part (the bits below the pass's digit), so tile b
+// holds the low values (V_{b-1}, V_b], V_b being the low part of its last
+// entry.  For such a v and any digit d,
+//   ptr[(d, v)] = (entries of d in tiles before b) + (entries of d in tile b
+//                 with low part < v),
+// because every earlier tile's entries have low parts <= V_{b-1} < v and
+// every later tile's have low parts >= V_b >= v.  Tile b writes exactly those
+// entries (the first tile from v = 0, the last up to the largest low value),
+// so every pointer entry is written once, by one tile, with no pass of its own.
+struct SeedPtrOut {
+    uint32_t* ptr;
+    uint64_t nkeys;   // 2^bits; ptr[nkeys] = count
+    uint32_t ndig;    // digit values of the last pass: 2^(bits - dshift)
+};
+
+// 3. stable scatter of one tile
+template <bool FIRST, bool HASH, bool LAST>
 __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
     SeedBuffers io, uint64_t count, uint32_t shift, uint32_t mask, uint32_t dshift,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, uint64_t ntiles) {
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, uint64_t ntiles,
+    uint32_t per_xcd, SeedPtrOut po) {
     __shared__ uint32_t cnt[kSeedWaves][kDigits];  // running counts, then wave offsets
     __shared__ uint32_t gbase[kDigits];            // global start of the tile's run of d
     __shared__ uint32_t tstart[kDigits];           // start of d in the tile's digit order
@@ -196,9 +222,14 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
     __shared__ uint64_t stage_h[HASH ? kSeedTile : 1];
     __shared__ uint32_t stage_k[HASH ? 1 : kSeedTile];
     __shared__ uint32_t stage_p[kSeedTile];
+    // Workgroups are dealt to the dies round-robin; each die takes a
+    // contiguous run of tiles, so that the line a tile's run of a digit (or of
+    // pointer entries) leaves partly written is completed by the next tile in
+    // the same L2.
+    const uint64_t b = (uint64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (b >= ntiles) return;  // uniform over the workgroup
     const int lane = lane_id();
     const int wv = wave_id();
-    const uint64_t b = blockIdx.x;
     for (int d = lane; d < kDigits; d += kWave) cnt[wv][d] = 0u;
     if (wv == 0) {
         for (int d = lane; d < kDigits; d += kWave) gbase[d] = totals[d];
@@ -208,6 +239,15 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
     }
     wave_lds_sync();
     const uint64_t below = (1ull << lane) - 1ull;
+    // LAST: the low parts of the previous tile's last entry and of this tile's
+    // last entry bound this tile's pointer entries; loaded early
+    const uint32_t lmask = LAST ? (1u << dshift) - 1u : 0u;  // dshift <= 24
+    uint32_t vprev = 0, vlast = 0;
+    if (LAST) {
+        const uint64_t t_end = (b + 1) * kSeedTile < count ? (b + 1) * kSeedTile : count;
+        if (b > 0) vprev = seed_in_key<FIRST, HASH>(io, b * kSeedTile - 1, shift, mask);
+        vlast = seed_in_key<FIRST, HASH>(io, t_end - 1, shift, mask);
+    }
     SeedItem<HASH> item[kSeedRounds];
     uint32_t rank[kSeedRounds];
     // every load of the tile first: the ranking rounds below are separated by
@@ -276,82 +316,73 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
         const uint32_t d = (it.key(shift, mask) >> dshift) & 0xFFu;
         seed_store<HASH>(io, (uint64_t)gbase[d] + (t - tstart[d]), it);
     }
-}
-
-// 4. pointer table: ptr[j] = number of sorted entries with key < j, for
-//    j = 0 .. nkeys: a merge of the implicit sequence 0 .. nkeys (A) with the
-//    sorted keys (B), A first on ties; when A's j is merged, the B entries
-//    merged before it are exactly those with key < j.  The merge path is cut
-//    into diagonals of kMergeTile steps (one workgroup each); a first kernel
-//    finds where each diagonal crosses A, so that every workgroup does the
-//    same amount of work however the keys are spread.
-
-// A's index at merge diagonal d: the number of A elements among the first d.
-template <bool HASH>
-__device__ __forceinline__ uint64_t merge_split(const uint64_t* hash, const uint32_t* keys,
-                                                uint32_t shift, uint32_t mask, uint64_t nA,
-                                                uint64_t nB, uint64_t d) {
-    uint64_t lo = d > nB ? d - nB : 0, hi = d < nA ? d : nA;
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        const uint64_t j = d - mid - 1;
-        const uint64_t bk = HASH ? seed_key(hash[j], shift, mask) : keys[j];
-        if (mid <= bk) lo = mid + 1;  // A[mid] = mid goes before B[j]
-        else hi = mid;
-    }
-    return lo;
-}
-
-template <bool HASH>
-__global__ void seed_ptr_split_kernel(const uint64_t* __restrict__ hash,
-                                      const uint32_t* __restrict__ keys, uint64_t count,
-                                      uint32_t shift, uint32_t mask, uint64_t nkeys,
-                                      uint64_t nblocks, uint32_t* __restrict__ splits) {
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t > nblocks) return;
-    const uint64_t nA = nkeys + 1, total = nA + count;
-    const uint64_t d = t * kPtrChunk < total ? t * kPtrChunk : total;
-    splits[t] = (uint32_t)merge_split<HASH>(hash, keys, shift, mask, nA, count, d);
-}
-
-template <bool HASH>
-__global__ __launch_bounds__(kSeedNT) void seed_ptr_merge_kernel(
-    const uint64_t* __restrict__ hash, const uint32_t* __restrict__ keys, uint64_t count,
-    uint32_t shift, uint32_t mask, uint64_t nkeys, const uint32_t* __restrict__ splits,
-    uint32_t* __restrict__ ptr) {
-    constexpr int per = kPtrChunk / kSeedNT;  // merge steps per thread
-    __shared__ uint32_t sB[kPtrChunk];        // this diagonal's B keys
-    __shared__ uint32_t sOut[kPtrChunk];      // ptr of this diagonal's A elements
-    const uint64_t nA = nkeys + 1, total = nA + count;
-    const uint64_t d0 = (uint64_t)blockIdx.x * kPtrChunk;
-    const uint64_t d1 = d0 + kPtrChunk < total ? d0 + kPtrChunk : total;
-    const uint64_t i0 = splits[blockIdx.x], i1 = splits[blockIdx.x + 1];
-    const uint64_t j0 = d0 - i0, j1 = d1 - i1;
-    const uint32_t na = (uint32_t)(i1 - i0), nb = (uint32_t)(j1 - j0);
-    for (uint32_t j = threadIdx.x; j < nb; j += kSeedNT)
-        sB[j] = HASH ? seed_key(hash[j0 + j], shift, mask) : keys[j0 + j];
-    __syncthreads();
-    // this thread's sub-diagonal [dt, dt + per) of the window
-    const uint32_t dt = threadIdx.x * per;
-    if (dt < na + nb) {
-        uint32_t lo = dt > nb ? dt - nb : 0, hi = dt < na ? dt : na;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) / 2;
-            if (i0 + mid <= (uint64_t)sB[dt - mid - 1]) lo = mid + 1;
-            else hi = mid;
-        }
-        uint32_t i = lo, j = dt - lo;
-        for (int step = 0; step < per && i + j < na + nb; ++step) {
-            if (i < na && (j >= nb || i0 + i <= (uint64_t)sB[j])) {
-                sOut[i] = (uint32_t)(j0 + j);
-                ++i;
-            } else {
-                ++j;
+    if constexpr (LAST) {
+        // this tile's pointer entries: low values vlo .. vhi of every digit
+        const uint64_t vlo = b == 0 ? 0ull : (uint64_t)(vprev & lmask) + 1;
+        const uint64_t vhi = b + 1 == ntiles ? lmask : vlast & lmask;
+        if (vhi + 1 <= vlo + kWave) {
+            // a short range (dense tables): entry j of d's run (low part l_j;
+            // runs are in input order, so the low parts ascend) owns v in
+            // (l_{j-1}, l_j], below which lie exactly j entries of the run;
+            // the first entry's range starts at vlo
+            for (uint32_t q = threadIdx.x; q < nb; q += kSeedNT) {
+                const uint32_t k = HASH ? seed_key(stage_h[q], shift, mask) : stage_k[q];
+                const uint32_t d = (k >> dshift) & 0xFFu;
+                const uint32_t s0 = tstart[d];
+                const uint64_t from =
+                    q > s0 ? (uint64_t)((HASH ? seed_key(stage_h[q - 1], shift, mask) : stage_k[q - 1]) & lmask) + 1
+                           : vlo;
+                const uint64_t to = (uint64_t)(k & lmask);
+                const uint32_t val = gbase[d] + (q - s0);
+                for (uint64_t v = from > vlo ? from : vlo; v <= to; ++v)
+                    po.ptr[((uint64_t)d << dshift) | v] = val;
+            }
+            // past a digit's last entry (or the whole range if the tile has
+            // none of it) all of the run lies below: per digit, where that
+            // starts and the value, then one sweep over (digit, v) so that
+            // neighbouring lanes store to neighbouring entries
+            uint32_t* tail_from = cnt[0];  // the rank counters are free by now
+            uint32_t* tail_val = cnt[1];
+            for (uint32_t d = threadIdx.x; d < po.ndig; d += kSeedNT) {
+                const uint32_t s0 = tstart[d];
+                const uint32_t s1 = d + 1 < (uint32_t)kDigits ? tstart[d + 1] : nb;
+                tail_from[d] = s1 > s0 ? ((HASH ? seed_key(stage_h[s1 - 1], shift, mask) : stage_k[s1 - 1]) & lmask) + 1u
+                                       : (uint32_t)vlo;
+                tail_val[d] = gbase[d] + (s1 - s0);
+            }
+            __syncthreads();
+            const uint32_t rng = (uint32_t)(vhi + 1 - vlo);  // 1 .. 64
+            for (uint32_t idx = threadIdx.x; idx < po.ndig * rng; idx += kSeedNT) {
+                const uint32_t d = idx / rng;
+                const uint32_t v = (uint32_t)vlo + (idx - d * rng);
+                if (v >= tail_from[d]) po.ptr[((uint64_t)d << dshift) | v] = tail_val[d];
+            }
+        } else {
+            // a long range (sparse tables): lanes take consecutive v, each
+            // counting the run's entries below v by a binary search
+            for (uint32_t d = (uint32_t)wv; d < po.ndig; d += kSeedWaves) {
+                const uint32_t s0 = tstart[d];
+                const uint32_t s1 = d + 1 < (uint32_t)kDigits ? tstart[d + 1] : nb;
+                for (uint64_t v = vlo + (uint64_t)lane; v <= vhi; v += kWave) {
+                    uint32_t lo = s0, hi = s1;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        const uint32_t k = HASH ? seed_key(stage_h[mid], shift, mask) : stage_k[mid];
+                        if ((k & lmask) < v) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    po.ptr[((uint64_t)d << dshift) | v] = gbase[d] + (lo - s0);
+                }
             }
         }
+        if (b + 1 == ntiles && threadIdx.x == 0) po.ptr[po.nkeys] = (uint32_t)count;
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < na; i += kSeedNT) ptr[i0 + i] = sOut[i];
+}
+
+__global__ void seed_fill_kernel(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -363,29 +394,38 @@ uint64_t seed_tiles(uint64_t count) { return (count + kSeedTile - 1) / kSeedTile
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
-template <bool FIRST, bool HASH>
+template <bool FIRST, bool HASH, bool LAST>
 void seed_pass(const SeedBuffers& io, uint64_t count, uint32_t shift, uint32_t mask,
-               uint32_t dshift, uint32_t* hist, uint32_t* totals, uint64_t nt, hipStream_t s) {
+               uint32_t dshift, uint32_t* hist, uint32_t* totals, uint64_t nt,
+               const SeedPtrOut& po, hipStream_t s) {
     hipLaunchKernelGGL((seed_hist_kernel<FIRST, HASH>), dim3((unsigned)nt), dim3(kSeedNT), 0, s,
                        io, count, shift, mask, dshift, hist, nt);
     hipLaunchKernelGGL(seed_scan_kernel, dim3(kDigits), dim3(kSeedNT), 0, s, hist, nt, totals);
-    hipLaunchKernelGGL((seed_scatter_kernel<FIRST, HASH>), dim3((unsigned)nt), dim3(kSeedNT), 0,
-                       s, io, count, shift, mask, dshift, hist, totals, nt);
+    const uint32_t per_xcd = (uint32_t)((nt + kXcds - 1) / kXcds);
+    hipLaunchKernelGGL((seed_scatter_kernel<FIRST, HASH, LAST>), dim3(per_xcd * kXcds),
+                       dim3(kSeedNT), 0, s, io, count, shift, mask, dshift, hist, totals, nt,
+                       per_xcd, po);
+}
+
+template <bool HASH>
+void seed_pass_any(bool first, bool last, const SeedBuffers& io, uint64_t count, uint32_t shift,
+                   uint32_t mask, uint32_t dshift, uint32_t* hist, uint32_t* totals, uint64_t nt,
+                   const SeedPtrOut& po, hipStream_t s) {
+    if (first && last) seed_pass<true, HASH, true>(io, count, shift, mask, dshift, hist, totals, nt, po, s);
+    else if (first) seed_pass<true, HASH, false>(io, count, shift, mask, dshift, hist, totals, nt, po, s);
+    else if (last) seed_pass<false, HASH, true>(io, count, shift, mask, dshift, hist, totals, nt, po, s);
+    else seed_pass<false, HASH, false>(io, count, shift, mask, dshift, hist, totals, nt, po, s);
 }
 
 }  // namespace
 
 // Workspace: two carries of (8-byte hash or 4-byte key, 4-byte position),
-// the digit-major tile histogram, the 256 digit totals and the merge-path
-// splits of the pointer fill.
-uint64_t merge_blocks(uint64_t count, uint32_t bits) {
-    return ((1ull << bits) + 1 + count + kPtrChunk - 1) / kPtrChunk;
-}
-
+// the digit-major tile histogram and the 256 digit totals.
 uint64_t seed_table_workspace_bytes(uint64_t count, uint32_t bits) {
+    (void)bits;
     const uint64_t nt = seed_tiles(count);
     return 2 * align256(8 * count) + 2 * align256(4 * count) + align256(4ull * kDigits * nt) +
-           align256(4ull * kDigits) + align256(4 * (merge_blocks(count, bits) + 1));
+           align256(4ull * kDigits);
 }
 
 int launch_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count, uint32_t bits,
@@ -404,52 +444,37 @@ int launch_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count,
     uint32_t* totals = reinterpret_cast<uint32_t*>(wp + 2 * align256(4 * count) +
                                                    align256(4ull * kDigits * nt));
     const bool with_hash = hash_out != nullptr;
-    // the sorted keys (or hashes) the pointer fill reads
-    const uint64_t* sorted_h = hash;
-    const uint32_t* sorted_k = nullptr;
-    if (count > 0) {
-        const int passes = (int)((bits + 7) / 8);
-        SeedBuffers io{};
-        io.hash_in = hash;
-        io.pos_in = pos;
-        for (int p = 0; p < passes; ++p) {
-            const bool last = p == passes - 1;
-            const int o = p & 1;
-            // outputs: the caller's arrays on the last pass, else a carry buffer
-            io.pos_out = last ? pos_out : carryP[o];
-            if (with_hash) io.hash_out = last ? hash_out : carryH[o];
-            else io.key_out = reinterpret_cast<uint32_t*>(carryH[o]);  // keys in the hash slots
-            const uint32_t dshift = 8u * (uint32_t)p;
-            if (p == 0) {
-                if (with_hash) seed_pass<true, true>(io, count, shift, mask, dshift, hist, totals, nt, s);
-                else seed_pass<true, false>(io, count, shift, mask, dshift, hist, totals, nt, s);
-            } else {
-                if (with_hash) seed_pass<false, true>(io, count, shift, mask, dshift, hist, totals, nt, s);
-                else seed_pass<false, false>(io, count, shift, mask, dshift, hist, totals, nt, s);
-            }
-            // this pass's outputs are the next pass's inputs
-            io.pos_in = io.pos_out;
-            if (with_hash) io.hash_in = io.hash_out;
-            else io.key_in = io.key_out;
-        }
-        if (with_hash) sorted_h = hash_out;
-        else sorted_k = io.key_in;
+    if (count == 0) {
+        // no entries: every pointer is 0
+        const uint64_t blocks = (nkeys + 1 + 255) / 256;
+        hipLaunchKernelGGL(seed_fill_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)),
+                           dim3(256), 0, s, ptr, nkeys + 1, 0u);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
     }
-    uint32_t* splits = reinterpret_cast<uint32_t*>(wp + 2 * align256(4 * count) +
-                                                   align256(4ull * kDigits * nt) +
-                                                   align256(4ull * kDigits));
-    const uint64_t nblocks = merge_blocks(count, bits);
-    const unsigned gs = (unsigned)((nblocks + 1 + kSeedNT - 1) / kSeedNT);
-    if (count > 0 && !with_hash) {
-        hipLaunchKernelGGL((seed_ptr_split_kernel<false>), dim3(gs), dim3(kSeedNT), 0, s, sorted_h,
-                           sorted_k, count, shift, mask, nkeys, nblocks, splits);
-        hipLaunchKernelGGL((seed_ptr_merge_kernel<false>), dim3((unsigned)nblocks), dim3(kSeedNT),
-                           0, s, sorted_h, sorted_k, count, shift, mask, nkeys, splits, ptr);
-    } else {
-        hipLaunchKernelGGL((seed_ptr_split_kernel<true>), dim3(gs), dim3(kSeedNT), 0, s, sorted_h,
-                           sorted_k, count, shift, mask, nkeys, nblocks, splits);
-        hipLaunchKernelGGL((seed_ptr_merge_kernel<true>), dim3((unsigned)nblocks), dim3(kSeedNT),
-                           0, s, sorted_h, sorted_k, count, shift, mask, nkeys, splits, ptr);
+    const int passes = (int)((bits + 7) / 8);
+    SeedPtrOut po;
+    po.ptr = ptr;
+    po.nkeys = nkeys;
+    po.ndig = 1u << (bits - 8u * (uint32_t)(passes - 1));
+    SeedBuffers io{};
+    io.hash_in = hash;
+    io.pos_in = pos;
+    for (int p = 0; p < passes; ++p) {
+        const bool last = p == passes - 1;
+        const int o = p & 1;
+        // outputs: the caller's arrays on the last pass, else a carry buffer
+        io.pos_out = last ? pos_out : carryP[o];
+        if (with_hash) io.hash_out = last ? hash_out : carryH[o];
+        else io.key_out = reinterpret_cast<uint32_t*>(carryH[o]);  // keys in the hash slots
+        const uint32_t dshift = 8u * (uint32_t)p;
+        if (with_hash)
+            seed_pass_any<true>(p == 0, last, io, count, shift, mask, dshift, hist, totals, nt, po, s);
+        else
+            seed_pass_any<false>(p == 0, last, io, count, shift, mask, dshift, hist, totals, nt, po, s);
+        // this pass's outputs are the next pass's inputs
+        io.pos_in = io.pos_out;
+        if (with_hash) io.hash_in = io.hash_out;
+        else io.key_in = io.key_out;
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -49,12 +49,15 @@ def test_fig1_example():
     check(torch, hh, pp, 6, 0)
 
 
-@pytest.mark.parametrize("bits", [1, 5, 8, 9, 16, 17, 24])
+@pytest.mark.parametrize("bits", [1, 5, 8, 9, 12, 13, 16, 17, 20, 24, 25])
 def test_sizes_and_widths(bits):
-    """Counts from 0 across several tiles with ragged tails; 1 to 3 radix passes."""
+    """Counts from 0 across several tiles with ragged tails, 1 to 4 radix
+    passes; the last pass writes the pointer table, each tile its share, so
+    the tile counts cover one tile, fewer tiles than dies, and several tiles
+    per die (36 tiles over 8 dies)."""
     torch = torch_cuda()
     rng = np.random.default_rng(100 + bits)
-    for count in (0, 1, 63, 64, 65, TILE - 1, TILE, TILE + 1, 3 * TILE + 777):
+    for count in (0, 1, 63, 64, 65, TILE - 1, TILE, TILE + 1, 3 * TILE + 777, 36 * TILE - 5):
         h, p = random_entries(rng, count)
         check(torch, h, p, bits, 64 - bits)
     h, p = random_entries(rng, 5000)
@@ -68,6 +71,9 @@ def test_heavy_and_degenerate_keys():
     torch = torch_cuda()
     rng = np.random.default_rng(7)
     h, p = random_entries(rng, 50_000, heavy=0.7)
+    check(torch, h, p, 20, 44)
+    # a key holding 10000 entries: its run spans several tiles
+    h, p = random_entries(rng, 50_000, heavy=0.2)
     check(torch, h, p, 20, 44)
     h2 = np.full(20_000, 0xDEADBEEF00000000, dtype=np.uint64)
     p2 = np.arange(20_000, dtype=np.uint32) * 3
@@ -151,3 +157,12 @@ def test_minimizer_counting_forward_lexicographic():
     assert np.array_equal(np.diff(host_u32(ptr).astype(np.int64)), counts)
     order = np.argsort(eh, kind="stable")
     assert np.array_equal(host_u32(po), ep[order])
+
+
+def test_fourteen_million_entries():
+    """A table larger than config 2's (14 M entries, 24 bits): 3419 tiles,
+    427 or 428 per die."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(11)
+    h, p = random_entries(rng, 14_000_000)
+    check(torch, h, p, 24, 40)
