@@ -47,6 +47,10 @@ def _bind(lib):
     ll = ctypes.c_longlong
     lib.oracle_sliding_sum.argtypes = [ctypes.c_int, u64, u32p, u64, u32p]
     lib.oracle_sliding_sum.restype = ll
+    lib.oracle_sliding_extremum_deque.argtypes = [ctypes.c_int, u64, u32p, u64, u32p]
+    lib.oracle_sliding_extremum_deque.restype = ll
+    lib.oracle_affine_windows_by_prefix.argtypes = [u64, u32p, u64, u32p]
+    lib.oracle_affine_windows_by_prefix.restype = ll
     lib.oracle_mix64.argtypes = [u64]
     lib.oracle_mix64.restype = u64
     lib.oracle_mix64_inv.argtypes = [u64]
@@ -114,6 +118,40 @@ def sliding_sum(op: str, w: int, x: np.ndarray, lib=None) -> np.ndarray:
                                _ptr(y, ctypes.c_uint32))
     if r < 0:
         raise ValueError("oracle_sliding_sum rejected op=%s w=%d" % (op, w))
+    assert r == cnt
+    return y
+
+
+def sliding_extremum_deque(op: str, w: int, x: np.ndarray, lib=None) -> np.ndarray:
+    """min or max over every window of w by the monotone deque, O(N)."""
+    lib = lib or load()
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    n = x.shape[0]
+    cnt = max(0, n - w + 1) if w >= 1 else 0
+    y = np.zeros(cnt, dtype=np.uint32)
+    r = lib.oracle_sliding_extremum_deque(OPS[op], w, _ptr(x, ctypes.c_uint32), n,
+                                          _ptr(y, ctypes.c_uint32))
+    if r < 0:
+        raise ValueError("oracle_sliding_extremum_deque rejected op=%s w=%d" % (op, w))
+    assert r == cnt
+    return y
+
+
+def affine_windows_by_prefix(w: int, x: np.ndarray, lib=None) -> np.ndarray:
+    """Affine windows of x (uint32[n, 2], every multiplier odd) as
+    P_i^{-1} o P_{i+w} from prefix compositions, O(N)."""
+    lib = lib or load()
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    if x.ndim != 2 or x.shape[1] != 2:
+        raise ValueError("affine input must be uint32[n, 2]")
+    n = x.shape[0]
+    cnt = max(0, n - w + 1) if w >= 1 else 0
+    y = np.zeros((cnt, 2), dtype=np.uint32)
+    r = lib.oracle_affine_windows_by_prefix(w, _ptr(x, ctypes.c_uint32), n, _ptr(y, ctypes.c_uint32))
+    if r == -2:
+        raise ValueError("affine_windows_by_prefix needs odd multipliers")
+    if r < 0:
+        raise ValueError("affine_windows_by_prefix rejected w=%d" % w)
     assert r == cnt
     return y
 
@@ -212,3 +250,96 @@ def seed_table(hash_, pos, bits: int, shift: int, lib=None):
     if r != 0:
         raise ValueError("oracle seed table rejected bits=%d shift=%d" % (bits, shift))
     return ptr, po[:p.size].copy(), ho[:h.size].copy()
+
+
+def host_threads() -> int:
+    """Threads this process may run on."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return max(1, os.cpu_count() or 1)
+
+
+def minimizers_batch_parallel(seqs, offsets, k: int, w: int, canonical: bool = True,
+                              hashed: bool = True, threads: int | None = None,
+                              split: bool = False):
+    """minimizers_batch over groups of consecutive reads on several threads.
+
+    Reads are independent sequences, so each group runs the same C routine on
+    its own reads (the call releases the interpreter lock); the groups'
+    results are concatenated with their read ids and offsets shifted."""
+    from concurrent.futures import ThreadPoolExecutor
+    lib = load()
+    s = _as_bytes(seqs)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nreads = off.size - 1
+    threads = threads or host_threads()
+    ngroups = max(1, min(nreads, 4 * threads))
+    # group boundaries at about equal numbers of bases
+    targets = np.linspace(0, float(off[-1]), ngroups + 1)
+    cuts = np.unique(np.concatenate([[0], np.searchsorted(off[1:].astype(np.float64), targets[1:-1],
+                                                          side="left") + 1, [nreads]]))
+    cuts = [int(c) for c in cuts if 0 <= c <= nreads]
+
+    def run(g):
+        r0, r1 = cuts[g], cuts[g + 1]
+        b0 = int(off[r0])
+        sub = s[b0:int(off[r1])]
+        h, p, rd, ro = minimizers_batch(sub, off[r0:r1 + 1] - np.uint64(b0), k, w, canonical,
+                                        hashed, lib=lib, split=split)
+        return h, p, rd + np.uint32(r0), ro
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(run, range(len(cuts) - 1)))
+    ro_all = np.zeros(nreads + 1, dtype=np.uint64)
+    base = 0
+    for g, (_, _, _, ro) in enumerate(parts):
+        r0, r1 = cuts[g], cuts[g + 1]
+        ro_all[r0:r1 + 1] = ro + np.uint64(base)
+        base += int(ro[-1])
+    if not parts:
+        return (np.zeros(0, np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint32), ro_all)
+    return (np.concatenate([q[0] for q in parts]), np.concatenate([q[1] for q in parts]),
+            np.concatenate([q[2] for q in parts]), ro_all)
+
+
+def minimizers_chunked(seq, k: int, w: int, canonical: bool = True, hashed: bool = True,
+                       threads: int | None = None, chunks: int | None = None,
+                       split: bool = False):
+    """Single-sequence minimizers computed in chunks of windows on several
+    threads; equals minimizers().
+
+    Chunk c owns windows [a_c, a_{c+1}).  It runs the deque routine on the
+    bases of windows a_c - 1 .. a_{c+1} - 1 (k + w - 1 bases of overlap with
+    the chunk before), so that the store-once rule at a_c sees window
+    a_c - 1's minimizer; the entry window a_c - 1 itself stores (it stores one
+    iff it has a minimizer) belongs to the chunk before and is dropped."""
+    from concurrent.futures import ThreadPoolExecutor
+    lib = load()
+    s = _as_bytes(seq)
+    n = s.size
+    nwin = window_bound(n, k, w)
+    threads = threads or host_threads()
+    chunks = chunks or 4 * threads
+    chunks = max(1, min(chunks, nwin))
+    starts = [nwin * c // chunks for c in range(chunks + 1)]
+    span = k + w - 1  # bases of one window
+
+    def run(c):
+        a, b = starts[c], starts[c + 1]
+        if a == b:
+            return np.zeros(0, np.uint64), np.zeros(0, np.uint32)
+        lead = 1 if c > 0 else 0
+        lo = a - lead
+        h, p = minimizers(s[lo:b - 1 + span], k, w, canonical, hashed, lib=lib, split=split)
+        drop = 0
+        if lead:
+            h1, _ = minimizers(s[lo:lo + span], k, w, canonical, hashed, lib=lib, split=split)
+            drop = h1.size
+        return h[drop:], (p[drop:] + np.uint32(lo)).astype(np.uint32)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(run, range(chunks)))
+    if not parts:
+        return np.zeros(0, np.uint64), np.zeros(0, np.uint32)
+    return np.concatenate([q[0] for q in parts]), np.concatenate([q[1] for q in parts])

@@ -15,6 +15,13 @@
  *   oracle_sliding_sum        Sec. 2.2, Eq. 2: y_i = x_i (+) ... (+) x_{i+w-1},
  *                             exactly w addends, as a left fold (the naive
  *                             O(wN) algorithm of Sec. 2.2).
+ *   oracle_sliding_extremum_deque
+ *                             the same outputs for min and max by the
+ *                             monotone deque (the O(N) "Dequeue" the paper
+ *                             compares against, Sec. 2.4, Sec. 4).
+ *   oracle_affine_windows_by_prefix
+ *                             the affine outputs for invertible maps (odd
+ *                             multipliers) from prefix compositions, O(N).
  *   oracle_kmers              Sec. 2.4: k-mers as a sliding sum of bases under
  *                             concatenation, written as the positional value
  *                             sum_j code(s_{i+j}) * 4^(k-1-j); the reverse
@@ -115,6 +122,93 @@ long long oracle_sliding_sum(int op, uint64_t w, const uint32_t *x, uint64_t n,
         }
     }
     return (long long)count;
+}
+
+/* The same outputs for ORC_MIN / ORC_MAX with the monotone double-ended
+ * queue the paper names as its O(N) comparison ("Dequeue", Sec. 2.4 and the
+ * Sec. 4 / Fig. 3 timings): the queue holds indices whose values strictly
+ * improve from back to front; a new value removes every queued value it
+ * matches or beats, the front leaves once it falls out of the window, and the
+ * front is each window's extremum.  Returns the output count, 0 when n < w,
+ * -1 for another operator or w = 0.  Used to check the kernels at sizes where
+ * the O(wN) fold is too slow. */
+long long oracle_sliding_extremum_deque(int op, uint64_t w, const uint32_t *x, uint64_t n,
+                                        uint32_t *y) {
+    if (w == 0 || (op != ORC_MIN && op != ORC_MAX)) return -1;
+    if (n < w) return 0;
+    uint64_t *dq = (uint64_t *)malloc((n < w ? n : w) * sizeof(uint64_t) + sizeof(uint64_t));
+    if (!dq) return -3;
+    const uint64_t cap = (n < w ? n : w) + 1;  /* ring buffer of queued indices */
+    uint64_t head = 0, size = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        while (size > 0) {
+            uint32_t back = x[dq[(head + size - 1) % cap]];
+            int beaten = op == ORC_MIN ? x[i] <= back : x[i] >= back;
+            if (!beaten) break;
+            --size;
+        }
+        dq[(head + size) % cap] = i;
+        ++size;
+        if (i + 1 >= w) {
+            uint64_t first = i + 1 - w; /* the window x[first .. i] */
+            while (dq[head] < first) {
+                head = (head + 1) % cap;
+                --size;
+            }
+            y[first] = x[dq[head]];
+        }
+    }
+    free(dq);
+    return (long long)(n - w + 1);
+}
+
+/* Inverse of an odd a mod 2^32 by Newton's iteration inv <- inv * (2 - a * inv):
+ * a * a == 1 mod 8 for odd a, and each step doubles the correct low bits. */
+static uint32_t inverse_odd(uint32_t a) {
+    uint32_t inv = a;
+    for (int it = 0; it < 5; ++it) inv = (uint32_t)(inv * (2u - a * inv));
+    return inv;
+}
+
+/* Affine windows for inputs whose multipliers are all odd (then every map
+ * z -> a z + b is invertible mod 2^32), by prefix compositions: with
+ * P_j = f_0 o f_1 o ... o f_{j-1}, the window W_i = f_i o ... o f_{i+w-1}
+ * satisfies P_{i+w} = P_i o W_i, so W_i = P_i^{-1} o P_{i+w}.  Two running
+ * prefixes (at i and at i + w) and the running inverse of the first make it
+ * O(N).  Returns the output count, 0 when n < w, -1 for w = 0, -2 when a
+ * multiplier is even.  A check of the kernels at sizes where the fold of
+ * oracle_sliding_sum is too slow; pinned to the fold. */
+long long oracle_affine_windows_by_prefix(uint64_t w, const uint32_t *x, uint64_t n,
+                                          uint32_t *y) {
+    if (w == 0) return -1;
+    if (n < w) return 0;
+    for (uint64_t i = 0; i < n; ++i)
+        if ((x[2 * i] & 1u) == 0) return -2;
+    /* P_w = f_0 o ... o f_{w-1} */
+    uint32_t pb_a = 1, pb_b = 0;
+    for (uint64_t j = 0; j < w; ++j) {
+        uint32_t na, nb;
+        affine_combine(pb_a, pb_b, x[2 * j], x[2 * j + 1], &na, &nb);
+        pb_a = na;
+        pb_b = nb;
+    }
+    uint32_t qa = 1, qb = 0; /* P_i^{-1}, starting from P_0 = identity */
+    for (uint64_t i = 0; i + w <= n; ++i) {
+        affine_combine(qa, qb, pb_a, pb_b, &y[2 * i], &y[2 * i + 1]);
+        if (i + w == n) break;
+        /* P_{i+1}^{-1} = f_i^{-1} o P_i^{-1}, with (a, b)^{-1} = (a^{-1}, -a^{-1} b) */
+        uint32_t ia = inverse_odd(x[2 * i]);
+        uint32_t ib = (uint32_t)(0u - ia * x[2 * i + 1]);
+        uint32_t na, nb;
+        affine_combine(ia, ib, qa, qb, &na, &nb);
+        qa = na;
+        qb = nb;
+        /* P_{i+w+1} = P_{i+w} o f_{i+w} */
+        affine_combine(pb_a, pb_b, x[2 * (i + w)], x[2 * (i + w) + 1], &na, &nb);
+        pb_a = na;
+        pb_b = nb;
+    }
+    return (long long)(n - w + 1);
 }
 
 /* ---------------------------------------------------------------------- */

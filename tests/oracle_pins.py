@@ -200,6 +200,56 @@ def pin_minmax_library(lib):
     assert np.array_equal(oracle.sliding_sum("max", 1, x, lib=lib), x)
 
 
+def pin_minmax_deque(lib):
+    """The O(N) deque gives the same min/max windows as numpy's reductions over
+    sliding-window views and as the fold: on random values with many ties, on
+    increasing, decreasing and constant runs (the queue's longest and shortest
+    states), for w from 1 to n and w > n (no output)."""
+    rng = np.random.default_rng(15)
+    cases = [rng.integers(0, 4, 700, dtype=np.uint32),
+             rng.integers(0, 1 << 32, 700, dtype=np.uint32),
+             np.arange(700, dtype=np.uint32), np.arange(700, 0, -1).astype(np.uint32),
+             np.full(700, 9, dtype=np.uint32),
+             np.concatenate([np.arange(300), np.arange(300, 0, -1), np.zeros(100)]).astype(np.uint32)]
+    for x in cases:
+        for w in (1, 2, 3, 7, 64, 699, 700):
+            v = sliding_window_view(x, w)
+            for op, red in (("min", v.min), ("max", v.max)):
+                got = oracle.sliding_extremum_deque(op, w, x, lib=lib)
+                assert np.array_equal(got, red(axis=1)), (op, w)
+                assert np.array_equal(got, oracle.sliding_sum(op, w, x, lib=lib)), (op, w)
+        assert oracle.sliding_extremum_deque("min", 701, x, lib=lib).size == 0
+    for bad in ("add", "affine"):
+        try:
+            oracle.sliding_extremum_deque(bad, 4, cases[0], lib=lib)
+        except ValueError:
+            continue
+        raise AssertionError("deque accepted " + bad)
+
+
+def pin_affine_prefix(lib):
+    """For odd multipliers the prefix formulation equals the fold of Eq. 2 at
+    every window length, including w = 1 (the input), w = n (one output) and
+    multipliers near 2^32; an even multiplier is refused."""
+    rng = np.random.default_rng(16)
+    for n in (1, 2, 9, 300):
+        a = rng.integers(0, 1 << 31, n, dtype=np.uint64).astype(np.uint32) * 2 + 1
+        a[::7] = 0xFFFFFFFF
+        b = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+        x = np.stack([a, b], axis=1)
+        for w in sorted({1, 2, 3, 8, n // 2 + 1, n}):
+            if w > n:
+                continue
+            got = oracle.affine_windows_by_prefix(w, x, lib=lib)
+            assert np.array_equal(got, oracle.sliding_sum("affine", w, x, lib=lib)), (n, w)
+    x = np.array([[3, 1], [4, 1], [5, 9]], dtype=np.uint32)
+    try:
+        oracle.affine_windows_by_prefix(2, x, lib=lib)
+    except ValueError:
+        return
+    raise AssertionError("an even multiplier was accepted")
+
+
 def pin_minmax_composition(lib):
     """Idempotent ops compose: S_a(S_b(x)) = S_{a+b-1}(x)."""
     rng = np.random.default_rng(14)
@@ -546,8 +596,8 @@ def pin_split_segments(lib):
 
 
 ALL_PINS = [
-    pin_sliding_bruteforce, pin_add_prefix_difference, pin_minmax_library,
-    pin_minmax_composition, pin_affine_reductions, pin_paper_algorithms, pin_mix64,
+    pin_sliding_bruteforce, pin_add_prefix_difference, pin_minmax_library, pin_minmax_deque,
+    pin_affine_prefix, pin_minmax_composition, pin_affine_reductions, pin_paper_algorithms, pin_mix64,
     pin_kmers_strings, pin_kmer_strand_symmetry, pin_fig2_worked_example,
     pin_minimizers_bruteforce, pin_minimizers_invariants, pin_minimizer_density, pin_batch,
     pin_fig1_seed_table, pin_seed_table_bruteforce, pin_seed_table_invariants,

@@ -183,3 +183,58 @@ def test_block_sizes(threads):
         assert np.array_equal(ro.cpu().numpy().view(np.uint64), ero), (threads, k, w)
         assert np.array_equal(host_u32(rd), er) and np.array_equal(host_u32(p), ep), (threads, k, w)
         assert np.array_equal(host_u64(h), eh), (threads, k, w)
+
+
+def _bucket_expected(bb, b, ero, arrays):
+    """The oracle's outputs of bucket b's reads, in the bucket's order."""
+    sel = np.nonzero(bb.bucket_of == b)[0]
+    starts = ero[sel].astype(np.int64)
+    counts = (ero[sel + 1] - ero[sel]).astype(np.int64)
+    before = np.cumsum(counts) - counts
+    idx = np.arange(int(counts.sum()), dtype=np.int64) - np.repeat(before, counts) + \
+        np.repeat(starts, counts)
+    bro = np.zeros(sel.size + 1, dtype=np.uint64)
+    np.cumsum(counts, out=bro[1:])
+    return [a[idx] for a in arrays], bro, np.repeat(np.arange(sel.size, dtype=np.uint32), counts)
+
+
+def test_config4_full_batch():
+    """The whole uneven-read workload (2,000,000 reads of 150 b plus 100,000
+    lognormal long reads, 1% N, 1.4 Gbases, k = 15, w = 10) in both launch
+    configurations the benchmark times -- one launch over every read, and the
+    tuned length buckets captured in one HIP graph -- every minimizer, read id
+    and per-read offset compared with the oracle run read by read."""
+    torch = torch_cuda()
+    from paper_1811_10074_amd import batch, tune
+    k, w = 15, 10
+    seqs, off = inputs.read_batch(n_short=2_000_000, n_long=100_000, seed=3)
+    print("config 4 full batch: oracle", flush=True)
+    eh, ep, er, ero = oracle.minimizers_batch_parallel(seqs, off, k, w)
+    print("config 4 full batch: one launch", flush=True)
+    runner = batch.BatchRunner(torch.from_numpy(seqs).cuda(), off, k, w)
+    runner.launch()
+    h, p, rd, ro = runner.result()
+    assert np.array_equal(ro.cpu().numpy().view(np.uint64), ero)
+    assert np.array_equal(host_u32(rd), er)
+    assert np.array_equal(host_u32(p), ep)
+    assert np.array_equal(host_u64(h), eh)
+    del runner, h, p, rd, ro
+    torch.cuda.empty_cache()
+    print("config 4 full batch: bucketed graph", flush=True)
+    sub = slice(0, max(off.size // 20, 2))
+    soff = off[sub] - off[0]
+    table, _ = tune.tune(seqs[: int(soff[-1])], soff, k, w, reps=2)
+    bb = batch.BucketedBatch(seqs, off, k, w, tune_table=table)
+    bb.capture()
+    for rep in range(2):
+        bb.replay()
+        torch.cuda.synchronize()
+        res = bb.results()
+        for b, (h, p, rd, ro) in res.items():
+            (xh, xp), xro, xrd = _bucket_expected(bb, b, ero, (eh, ep))
+            assert np.array_equal(ro.cpu().numpy().view(np.uint64), xro), (rep, b)
+            assert np.array_equal(host_u32(rd), xrd), (rep, b)
+            assert np.array_equal(host_u32(p), xp), (rep, b)
+            assert np.array_equal(host_u64(h), xh), (rep, b)
+    del bb
+    torch.cuda.empty_cache()

@@ -94,3 +94,31 @@ def test_denser_than_the_copy_back_estimate():
     check(got, seqs, off)
     check(alone, rnd, np.array([0, rnd.size], dtype=np.uint64))
     assert got.read_offsets[1] == 20000 - K - W + 2  # every window of the poly-A read
+
+
+def test_config5_sized_requests_alone_and_mixed():
+    """Requests of the serving workload's full size range (1 to 4096 reads of
+    the uneven-read mix, several Mbases at the top): the largest requests of
+    ten seconds of Poisson arrivals plus a spread of others, each served alone
+    and then all submitted at once; every result equals the oracle's."""
+    torch_cuda()
+    from paper_1811_10074_amd.serve import GPUExecutor, Server
+    allreq = [(s, o) for _, s, o in inputs.poisson_requests(rate=200.0, duration_s=10.0,
+                                                            max_reads=4096, seed=4)]
+    by_size = sorted(range(len(allreq)), key=lambda i: int(allreq[i][1][-1]))
+    pick = sorted(set(by_size[-6:]) | set(by_size[:: max(1, len(by_size) // 30)]))
+    reqs = [allreq[i] for i in pick]
+    assert max(int(o[-1]) for _, o in reqs) > 2_000_000
+    assert max(o.size - 1 for _, o in reqs) > 1000
+    ex = GPUExecutor(K, W, arena_bytes=4 << 30, streams=3)
+    srv = Server(ex, K, W).start()
+    alone = [srv.submit(s, o).result(timeout=120) for s, o in reqs]
+    futs = [srv.submit(s, o) for s, o in reqs]
+    mixed = [f.result(timeout=120) for f in futs]
+    srv.stop()
+    for (s, o), a, m in zip(reqs, alone, mixed):
+        h, p, r, ro = oracle.minimizers_batch_parallel(s, o, K, W)
+        for res in (a, m):
+            assert np.array_equal(res.read_offsets, ro)
+            assert np.array_equal(res.pos, p) and np.array_equal(res.hash, h)
+    assert srv.arena.free_bytes == srv.arena.size

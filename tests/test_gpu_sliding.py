@@ -164,31 +164,43 @@ def _sample_check(torch, op, w, x, y, samples, rng):
 
 
 @pytest.mark.parametrize("op", ["add", "min", "max", "affine"])
-def test_config3_full_size_sampled(op):
+def test_config3_full_size(op):
     """N = 2^28 at every window of the sweep, in the bench's launch
-    configuration; sampled outputs against the oracle one by one, and for +
-    the prefix-difference identity over every output."""
+    configuration, every output compared: min and max against the oracle's
+    O(N) deque, + against the prefix-difference identity, affine (odd
+    multipliers, so every map is invertible) against prefix compositions;
+    and 300 sampled outputs against the fold of Eq. 2 itself."""
     torch = torch_cuda()
     import paper_1811_10074_amd as sws
     n = 1 << 28
     rng = np.random.default_rng(99)
     x = inputs.affine_pairs(n, seed=2, odd=True) if op == "affine" else inputs.uniform_u32(n, seed=2)
     t = dev(x, torch)
-    paths = {"min": ["generic", "log"], "max": ["generic", "log"], "add": ["generic", "prefix"],
-             "affine": ["generic"]}[op]
+    paths = {"min": ["auto", "generic", "log"], "max": ["auto", "generic", "log"],
+             "add": ["auto", "generic", "prefix"], "affine": ["auto", "generic"]}[op]
+    pfx = None
+    if op == "add":
+        pfx = np.zeros(n + 1, dtype=np.uint64)
+        np.cumsum(x, dtype=np.uint64, out=pfx[1:])
     for w in (4, 16, 64, 256, 1024):
+        print("config 3 full size: op=%s w=%d" % (op, w), flush=True)
+        if op in ("min", "max"):
+            exp = oracle.sliding_extremum_deque(op, w, x)
+        elif op == "affine":
+            exp = oracle.affine_windows_by_prefix(w, x)
+        else:
+            exp = ((pfx[w:] - pfx[:-w]) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
         for path in paths:
             y = sws.sliding_sum(op, w, t, path=path)
             torch.cuda.synchronize()
             yh = host_u32(y)
             del y
-            _sample_check(torch, op, w, x, yh, 300, rng)
-            if op == "add":
-                pfx = np.zeros(n + 1, dtype=np.uint64)
-                np.cumsum(x, dtype=np.uint64, out=pfx[1:])
-                exp = ((pfx[w:] - pfx[:-w]) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
-                assert np.array_equal(yh, exp), w
-                del pfx, exp
+            if not np.array_equal(yh, exp):
+                bad = np.nonzero(yh.reshape(len(yh), -1) != exp.reshape(len(exp), -1))[0]
+                raise AssertionError("op=%s w=%d path=%s: %d mismatches, first at %d"
+                                     % (op, w, path, bad.size, bad[0]))
+            _sample_check(torch, op, w, x, yh, 100, rng)
+        del exp
 
 
 def _slab(op, w):
