@@ -63,6 +63,50 @@ def profiled_traffic(profile_name):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def profile_summary(profile_name):
+    """The key: value lines and the per-kernel average durations (ns) of a
+    committed rocprofv3 summary under profiles/, or None when the kernel's
+    source changed since it was taken (or the summary records no source)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile_name)
+    if not os.path.exists(path):
+        return None
+    fields, kernels, in_table = {}, {}, False
+    for line in open(path):
+        if line.startswith("Kernel statistics"):
+            in_table = True
+            continue
+        if in_table:
+            parts = line.split()
+            if not parts:
+                in_table = False
+            elif parts[0] != "kernel" and len(parts) >= 5 and parts[-4].isdigit():
+                kernels[" ".join(parts[:-4])] = float(parts[-3])
+            continue
+        if ":" in line:
+            k_, v_ = line.strip().split(":", 1)
+            fields[k_.strip()] = v_.strip()
+    srcs = [os.path.join(ROOT, f.strip()) for f in fields.get("source", "").split(",") if f.strip()]
+    if not srcs or not all(os.path.isfile(f) for f in srcs):
+        return None
+    h = hashlib.sha256()
+    for f in srcs:
+        h.update(open(f, "rb").read())
+    if h.hexdigest() != fields.get("source_sha256"):
+        return None
+    return {"fields": fields, "kernels": kernels}
+
+
+def profiled_kernel_us(profile_name, kernel_substr):
+    prof = profile_summary(profile_name)
+    if prof is None:
+        return None
+    for name, ns in prof["kernels"].items():
+        if kernel_substr in name:
+            return ns / 1e3
+    return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -106,30 +150,87 @@ def time_back_to_back(torch, fn, steps, warmup):
     return start.elapsed_time(end) / steps
 
 
-def cpu_baseline(seq_np, k, w, target_s=10.0):
-    """The oracle's deque minimizer on a prefix of the same sequence, repeated
-    until about target_s seconds of CPU work."""
-    import numpy as np
-    import oracle
+def cpu_info():
+    """The host CPU as /proc/cpuinfo states it (model name, family/model/
+    stepping, vector extensions) and the threads this process may use."""
+    info = {}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if ":" not in line:
+                if info:
+                    break
+                continue
+            key, val = (x.strip() for x in line.split(":", 1))
+            if key in ("model name", "cpu family", "model", "stepping", "flags") and key not in info:
+                info[key] = val
+    except OSError:
+        pass
+    flags = set(info.pop("flags", "").split())
+    info["vector_extensions"] = [f for f in ("avx", "avx2", "avx512f", "avx512bw", "avx512vl")
+                                 if f in flags]
+    info.setdefault("model name", platform.processor())
+    info["threads_available"] = len(os.sched_getaffinity(0))
+    return info
 
-    sample = seq_np[: 1 << 24]
+
+def _timed(fn, target_s, max_reps):
+    """Repeats fn until about target_s seconds have passed; returns (reps, s)."""
     t0 = time.perf_counter()
     reps = 0
     while True:
-        oracle.minimizers(sample, k, w)
+        fn()
         reps += 1
         el = time.perf_counter() - t0
-        if el >= target_s or reps >= 8:
-            break
-    rate = reps * sample.size / el / 1e9
-    try:
-        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
-    except Exception:
-        model = platform.processor()
-    return {"value": rate, "unit": "Gbases/s", "cores": 1, "kind": "oracle",
-            "sample": "deque minimizers (k=15, w=10) over the first 2^24 bases of the same "
-                      "sequence, %d repetitions, %.1f s, single thread" % (reps, el),
-            "cpu": model, "host_threads_available": len(os.sched_getaffinity(0))}
+        if el >= target_s or reps >= max_reps:
+            return reps, el
+
+
+def _sliding_chunked(oracle, op, w, x, threads):
+    """The oracle's fold (Eq. 2, O(wN)) over contiguous output ranges on
+    several threads; each range reads w - 1 inputs past its end."""
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    cnt = x.shape[0] - w + 1
+    cuts = [cnt * i // (4 * threads) for i in range(4 * threads + 1)]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda c: oracle.sliding_sum(op, w, x[cuts[c]:cuts[c + 1] + w - 1]),
+                            range(4 * threads)))
+    return np.concatenate(parts)
+
+
+def cpu_baseline(seq_np, k, w, target_s=8.0):
+    """The oracle (test infrastructure) on this host's cores, as a baseline
+    only: deque minimizers over chunks of the same sequence on every thread
+    this process may use (chunks of windows overlapping by k + w - 1 bases),
+    single-threaded for reference, and the naive O(wN) sliding sums of the
+    N = 2^20 and N = 2^28 workloads at w = 16 (the latter on a 2^26 prefix)."""
+    import numpy as np
+    import oracle
+    from paper_1811_10074_amd import inputs
+
+    threads = min(16, len(os.sched_getaffinity(0)))
+    out = {"kind": "oracle", "unit": "Gbases/s", "cores": threads, "cpu": cpu_info()}
+    # multi-threaded: the whole 64-Mbase sequence, chunked
+    reps, el = _timed(lambda: oracle.minimizers_chunked(seq_np, k, w, threads=threads), target_s, 20)
+    out["value"] = reps * seq_np.size / el / 1e9
+    out["sample"] = ("deque minimizers (k=%d, w=%d) over the whole %d-base sequence in %d chunks "
+                     "on %d threads, %d repetitions, %.1f s" % (k, w, seq_np.size, 4 * threads,
+                                                               threads, reps, el))
+    # one thread, a 2^24-base prefix
+    pre = seq_np[: 1 << 24]
+    reps1, el1 = _timed(lambda: oracle.minimizers(pre, k, w), target_s / 2, 8)
+    out["single_thread"] = {"Gbases/s": reps1 * pre.size / el1 / 1e9,
+                            "sample": "first 2^24 bases, %d repetitions, %.1f s" % (reps1, el1)}
+    # naive sliding sums (Eq. 2 as one fold per output), Gelem/s of input
+    sl = {}
+    x1 = inputs.uniform_u32(1 << 20, seed=0)
+    x3 = inputs.uniform_u32(1 << 26, seed=2)
+    for name, x in (("n2^20_w16", x1), ("n2^28_w16_prefix2^26", x3)):
+        for op in ("min", "add"):
+            r, e = _timed(lambda: _sliding_chunked(oracle, op, 16, x, threads), target_s / 8, 50)
+            sl["%s_%s" % (name, op)] = round(r * x.size / e / 1e9, 3)
+    out["sliding_naive_Gelem_s"] = sl
+    return out
 
 
 def bench_sliding(torch, steps, warmup, quick):
@@ -143,6 +244,19 @@ def bench_sliding(torch, steps, warmup, quick):
     for op in ("min", "add"):
         ms, med, _ = time_launches(torch, lambda: sws.sliding_sum(op, 16, x1, out=y1), 50, 10)
         out["n2^20_w16_%s_us" % op] = round(med * 1000, 2)
+        # the device side alone: 100 calls captured in one HIP graph, so that
+        # the host's per-call cost (ctypes, argument checks) stays out
+        g = torch.cuda.CUDAGraph()
+        sws.sliding_sum(op, 16, x1, out=y1)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            for _ in range(100):
+                sws.sliding_sum(op, 16, x1, out=y1)
+        g.replay()
+        torch.cuda.synchronize()
+        gms = time_back_to_back(torch, g.replay, 10, 2)
+        out["n2^20_w16_%s_device_us" % op] = round(gms * 1e3 / 100, 2)
+        del g
     n = 1 << 28
     x = torch.from_numpy(inputs.uniform_u32(n, seed=2).view(np.int32)).cuda()
     xa = None if quick else torch.from_numpy(inputs.affine_pairs(n, seed=2).view(np.int32)).cuda()
@@ -268,7 +382,7 @@ def bench_serve(torch, quick):
     from paper_1811_10074_amd.serve import GPUExecutor, Server, latency_stats
 
     k, w = 19, 19
-    dur = 3.0 if quick else 10.0
+    dur = 3.0 if quick else 60.0
     log("generating %.0f s of Poisson requests" % dur)
     reqs = inputs.poisson_requests(rate=200.0, duration_s=dur, seed=4)
     bases = sum(int(o[-1]) for _, _, o in reqs)
@@ -333,13 +447,35 @@ def profile_run(torch, args):
         r = sws.MinimizerRunner(n, 15, 10)
         ms, med, _ = time_launches(torch, lambda: r.launch(seq=seq), args.steps, args.warmup)
         print(json.dumps({"kernel": "minimizer", "ms_per_step": ms, "count": int(r.count.item())}))
-    else:
-        n = 1 << 28
-        x = torch.from_numpy(inputs.uniform_u32(n, seed=2).view(np.int32)).cuda()
-        y = torch.empty(n - 15, dtype=torch.int32, device="cuda")
-        ms, med, _ = time_launches(torch, lambda: sws.sliding_sum("add", 16, x, path="generic", out=y),
+    elif args.profile in ("sliding", "affine1024", "config1"):
+        op, w, n, path = {"sliding": ("add", 16, 1 << 28, "generic"),
+                          "affine1024": ("affine", 1024, 1 << 28, "auto"),
+                          "config1": ("min", 16, 1 << 20, "auto")}[args.profile]
+        x = inputs.affine_pairs(n, seed=2) if op == "affine" else \
+            inputs.uniform_u32(n, seed=0 if n == 1 << 20 else 2)
+        x = torch.from_numpy(x.view(np.int32)).cuda()
+        y = torch.empty((n - w + 1, 2) if op == "affine" else (n - w + 1,), dtype=torch.int32,
+                        device="cuda")
+        ms, med, _ = time_launches(torch, lambda: sws.sliding_sum(op, w, x, path=path, out=y),
                                    args.steps, args.warmup)
-        print(json.dumps({"kernel": "sliding add w=16 n=2^28", "ms_per_step": ms}))
+        print(json.dumps({"kernel": "sliding %s w=%d n=%d path=%s" % (op, w, n, path),
+                          "ms_per_step": ms}))
+    elif args.profile == "seedtable":
+        n = 1 << 26
+        seq = torch.from_numpy(inputs.dna(n, seed=1)).cuda()
+        r = sws.MinimizerRunner(n, 15, 10)
+        r.launch(seq=seq)
+        h, p = r.result()
+        st = sws.SeedTableRunner(h.numel(), 24)
+        ms, med, _ = time_launches(torch, lambda: st.launch(h, p, 40), args.steps, args.warmup)
+        print(json.dumps({"kernel": "seed table 24 bits", "entries": h.numel(), "ms_per_step": ms}))
+    elif args.profile == "batch":
+        from paper_1811_10074_amd import batch
+        seqs, off = inputs.read_batch(n_short=2_000_000, n_long=100_000, seed=3)
+        runner = batch.BatchRunner(torch.from_numpy(seqs).cuda(), off, 15, 10)
+        ms, med, _ = time_launches(torch, runner.launch, args.steps, args.warmup)
+        print(json.dumps({"kernel": "batched minimizers, config 4, one launch", "ms_per_step": ms,
+                          "bases": int(off[-1])}))
 
 
 def main():
@@ -351,7 +487,8 @@ def main():
     ap.add_argument("--primary-only", action="store_true",
                     help="only the timed minimizer steps (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile", choices=["minimizer", "sliding"],
+    ap.add_argument("--profile", choices=["minimizer", "sliding", "affine1024", "config1",
+                                          "seedtable", "batch"],
                     help="run only a 1-GiB plain copy (counter calibration) and the named kernel "
                          "--steps times, for rocprofv3")
     args = ap.parse_args()
@@ -391,6 +528,22 @@ def main():
         print(json.dumps({"metric": METRIC, "value": value, "ms_per_step": ms, "count": count}))
         return
 
+    # the same step with the 256 MB Infinity Cache flushed first: a 512 MiB
+    # fill before every call, the call alone between the events
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    cold = []
+    for i in range(args.warmup + args.steps):
+        flush.fill_(i & 0xFF)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        step()
+        b.record()
+        if i >= args.warmup:
+            cold.append((a, b))
+    torch.cuda.synchronize()
+    ms_cold = sum(a.elapsed_time(b) for a, b in cold) / len(cold)
+    del flush
+
     algo_bytes = n + 12 * count  # ASCII in, (u64 hash, u32 pos) out
     line = {
         "metric": METRIC,
@@ -415,15 +568,34 @@ def main():
             "unit": "Tops/s",
             "frac": round(ALU_OPS_PER_BASE * n / (ms / 1e3) / 1e12 / ALU_PEAK_TOPS, 3),
             "traffic": profiled_traffic("minimizer_wave_kernel_64Mbases_k15_w10.txt"),
+            "ops_per_base_modelled": ALU_OPS_PER_BASE,
         },
         "hbm": {"algorithmic_bytes": algo_bytes,
                 "GB/s": round(algo_bytes / (ms / 1e3) / 1e9, 1),
-                "frac_of_peak": round(algo_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+                "frac_of_peak": round(algo_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "note": "back-to-back steps: the 64 MB input and 146 MB output stay in the "
+                        "256 MB Infinity Cache; dram_cold is the same step after a flush"},
+        "dram_cold": {"ms_per_step": round(ms_cold, 5),
+                      "Gbases/s": round(n / (ms_cold / 1e3) / 1e9, 2),
+                      "GB/s": round(algo_bytes / (ms_cold / 1e3) / 1e9, 1),
+                      "frac_of_peak": round(algo_bytes / (ms_cold / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "flush": "512 MiB fill before each step, outside the timed interval"},
         "minimizers_per_step": count,
         "median_ms": round(med, 5),
         "input_2bit": {"Gbases/s": round(n / (ms2 / 1e3) / 1e9, 2), "ms_per_step": round(ms2, 5),
                        "same_count": count2 == count},
     }
+    # the committed rocprofv3 summaries of the same kernel (when its source
+    # is unchanged since): its average duration, and the lane operations its
+    # VALU instructions issue per base against the modelled count
+    kus = profiled_kernel_us("minimizer_wave_kernel_64Mbases_k15_w10.txt", "minimizer_wave_kernel")
+    if kus:
+        line["roofline"]["profiled_kernel_us"] = round(kus, 2)
+        line["roofline"]["frac_at_profiled_kernel_time"] = round(
+            ALU_OPS_PER_BASE * n / (kus / 1e6) / 1e12 / ALU_PEAK_TOPS, 3)
+    sq = profile_summary("minimizer_wave_kernel_64Mbases_k15_w10_sq_counters.txt")
+    if sq and "valu_lane_ops_per_base" in sq["fields"]:
+        line["roofline"]["ops_per_base_issued"] = float(sq["fields"]["valu_lane_ops_per_base"])
     # the standalone steps a3 and a4 on the same sequence
     msp = time_back_to_back(torch, lambda: sws.pack2bit(seq), args.steps, args.warmup)
     msk = time_back_to_back(torch, lambda: sws.kmers(seq, k), args.steps, args.warmup)

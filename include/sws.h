@@ -41,8 +41,10 @@ extern "C" {
 /* 2: seed tables, the prefix-difference and scalar-input paths, SWS_SPLIT_AT_INVALID,
  *    SWS_WORKSPACE_KEPT (all additions; no call changed its meaning).
  * 3: sws_minimizers_batch_ex takes the workgroup size per call; the process-wide
- *    sws_set_minimizer_block is gone; sws_set_sliding_waves is per thread. */
-#define SWS_ABI_VERSION 3u
+ *    sws_set_minimizer_block is gone; sws_set_sliding_waves is per thread.
+ * 4: sws_sliding_sum_workspace / sws_sliding_sum_ws (windows of any length) and
+ *    sws_minimizers_noalloc (additions; no call changed its meaning). */
+#define SWS_ABI_VERSION 4u
 
 typedef enum {
     SWS_OK = 0,
@@ -138,6 +140,32 @@ int sws_sliding_sum(int op, uint64_t w, const void *x, uint64_t n, void *y, hipS
  * SWS_ERR_UNSUPPORTED. */
 int sws_sliding_sum_ex(int op, uint64_t w, const void *x, uint64_t n, void *y, int path,
                        hipStream_t s);
+
+/*
+ * Windows of any length.  sws_sliding_sum and sws_sliding_sum_ex serve
+ * w <= 2048 (the log path to 4096, the scalar path to 64) and return
+ * SWS_ERR_UNSUPPORTED above.  These two serve every w >= 1 (Eq. 2 has no
+ * bound on w): on SWS_PATH_AUTO and SWS_PATH_GENERIC, a window longer than
+ * 2048 is computed by the same segment identity as the generic path with
+ * segments of w elements cut into chunks of 2048: the window at offset o of a
+ * segment is the segment's suffix from o followed by the next segment's prefix
+ * up to o - 1, and per-chunk sums (in the workspace) carry both across chunks.
+ * Any associative op; x is read three times.  SWS_PATH_LOG keeps its limit
+ * (4096), SWS_PATH_PREFIX its limit (2048), SWS_PATH_SCALAR its limit (64).
+ */
+
+/* Workspace bytes sws_sliding_sum_ws needs for (op, w, n, path): 0 when the
+ * request takes a path without scratch (w <= 2048, or a path other than AUTO
+ * and GENERIC), else 3 values per chunk of 2048 offsets per segment of w.
+ * Errors: SWS_ERR_INVALID (op, path, w = 0, bytes null). */
+int sws_sliding_sum_workspace(int op, uint64_t w, uint64_t n, int path, uint64_t *bytes);
+
+/* As sws_sliding_sum_ex, for any w.  workspace: ws_bytes bytes of device
+ * scratch, 8-byte aligned, at least sws_sliding_sum_workspace(op, w, n, path)
+ * (may be NULL when that is 0); contents on entry do not matter.
+ * Errors: as sws_sliding_sum_ex, plus SWS_ERR_WORKSPACE. */
+int sws_sliding_sum_ws(int op, uint64_t w, const void *x, uint64_t n, void *y, int path,
+                       void *workspace, uint64_t ws_bytes, hipStream_t s);
 
 /* ------------------------------------------------------------------------ */
 /* 2-bit packing, k-mers.                                                     */

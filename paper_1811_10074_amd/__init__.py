@@ -79,9 +79,14 @@ def sliding_sum(op: str, w: int, x, path: str = "auto", out=None):
         out = torch.empty(shape, dtype=x.dtype, device=x.device)
     elif tuple(out.shape) != shape or out.dtype != x.dtype:
         raise ValueError("out must have shape %s and dtype %s" % (shape, x.dtype))
-    st = _lib.load().sws_sliding_sum_ex(_lib.OPS[op], w, _ptr(x), n, _ptr(out),
-                                         _lib.PATHS[path], _stream())
-    check(st, "sws_sliding_sum_ex")
+    lib = _lib.load()
+    b = ctypes.c_uint64(0)
+    check(lib.sws_sliding_sum_workspace(_lib.OPS[op], w, n, _lib.PATHS[path], ctypes.byref(b)),
+          "sws_sliding_sum_workspace")
+    ws = torch.empty(int(b.value), dtype=torch.uint8, device=x.device) if b.value else None
+    st = lib.sws_sliding_sum_ws(_lib.OPS[op], w, _ptr(x), n, _ptr(out), _lib.PATHS[path],
+                                _ptr(ws), int(b.value), _stream())
+    check(st, "sws_sliding_sum_ws")
     return out
 
 

@@ -38,6 +38,8 @@ _SIGNATURES = {
     "sws_status_str": (ctypes.c_char_p, [c_int]),
     "sws_sliding_sum": (c_int, [c_int, c_u64, c_vp, c_u64, c_vp, c_vp]),
     "sws_sliding_sum_ex": (c_int, [c_int, c_u64, c_vp, c_u64, c_vp, c_int, c_vp]),
+    "sws_sliding_sum_workspace": (c_int, [c_int, c_u64, c_u64, c_int, ctypes.POINTER(c_u64)]),
+    "sws_sliding_sum_ws": (c_int, [c_int, c_u64, c_vp, c_u64, c_vp, c_int, c_vp, c_u64, c_vp]),
     "sws_pack2bit": (c_int, [c_vp, c_u64, c_vp, c_vp, c_vp]),
     "sws_kmers": (c_int, [c_vp, c_u64, c_u32, c_u32, c_vp, c_vp]),
     "sws_minimizers_workspace": (c_int, [c_u64, c_u32, c_u32, ctypes.POINTER(c_u64)]),

@@ -161,6 +161,52 @@ int sws_sliding_sum(int op, uint64_t w, const void* x, uint64_t n, void* y, hipS
     return sws_sliding_sum_ex(op, w, x, n, y, SWS_PATH_AUTO, s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Windows above one slab go to the wide path on AUTO and GENERIC; LOG keeps
+// its own limit, PREFIX and SCALAR do not serve them.
+bool takes_wide_path(uint64_t w, int path) {
+    return w > sws::generic_max_window() && (path == SWS_PATH_AUTO || path == SWS_PATH_GENERIC);
+}
+
+int check_sliding_args(int op, uint64_t w, int path) {
+    if (op < SWS_OP_ADD_U32 || op > SWS_OP_AFFINE_U32) return SWS_ERR_INVALID;
+    if (path < SWS_PATH_AUTO || path > SWS_PATH_SCALAR) return SWS_ERR_INVALID;
+    if (w == 0) return SWS_ERR_INVALID;
+    return SWS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sws_sliding_sum_workspace(int op, uint64_t w, uint64_t n, int path, uint64_t* bytes) {
+    if (bytes == nullptr) return SWS_ERR_INVALID;
+    const int st = check_sliding_args(op, w, path);
+    if (st != SWS_OK) return st;
+    *bytes = (n >= w && takes_wide_path(w, path)) ? sws::wide_workspace_bytes(op, n, w) : 0;
+    return SWS_OK;
+}
+
+int sws_sliding_sum_ws(int op, uint64_t w, const void* x, uint64_t n, void* y, int path,
+                       void* workspace, uint64_t ws_bytes, hipStream_t s) {
+    const int st = check_sliding_args(op, w, path);
+    if (st != SWS_OK) return st;
+    if (!takes_wide_path(w, path)) return sws_sliding_sum_ex(op, w, x, n, y, path, s);
+    if (n < w) return SWS_OK;
+    if (x == nullptr || y == nullptr) return SWS_ERR_INVALID;
+    const uintptr_t align = op == SWS_OP_AFFINE_U32 ? 8u : 4u;
+    if (((uintptr_t)x | (uintptr_t)y) & (align - 1u)) return SWS_ERR_INVALID;
+    if (n >= (1ull << 40)) return SWS_ERR_UNSUPPORTED;  // grid of n / 2048 chunk workgroups
+    if (workspace == nullptr || ws_bytes < sws::wide_workspace_bytes(op, n, w) ||
+        ((uintptr_t)workspace & 7u))
+        return SWS_ERR_WORKSPACE;
+    return sws::launch_sliding_wide(op, x, n, w, y, n - w + 1, workspace, s) == 0 ? SWS_OK
+                                                                                 : SWS_ERR_DEVICE;
+}
+
 int sws_pack2bit(const uint8_t* seq, uint64_t n, uint32_t* packed, uint32_t* invalid,
                  hipStream_t s) {
     if (n == 0) return SWS_OK;

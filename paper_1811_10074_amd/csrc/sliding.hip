@@ -910,6 +910,255 @@ int launch_sliding_prefix(int op, const void* x, uint64_t n, uint32_t w, void* y
                                       : launch_generic<OpAdd, 16, 2, true>(x, n, w, y, count, tw, s);
 }
 
+// ---------------------------------------------------------------------------
+// Wide windows (w above one slab, any length).  The segments of the generic
+// path, [a w, (a+1) w), are now longer than a slab.  The window starting at
+// offset o of segment A = a is A's suffix from o followed by the prefix of
+// B = a + 1 up to offset o - 1:
+//     y_{a w + o} = Sf_A(o) (+) Pf_B(o - 1),     Pf_B(-1) = the identity,
+// so both operands sit at the same offset.  With chunks of T = 2048 offsets:
+//   1. wide_chunk_sum: the sum of every chunk (a, c);
+//   2. wide_chunk_scan: per segment, the sum of the chunks after c (for A's
+//      suffixes) and before c (for B's prefixes);
+//   3. wide_out: output chunk (a, c) = in-chunk suffixes of A's chunk c with
+//      the later chunks' sum, in-chunk exclusive prefixes of B's chunk c after
+//      the earlier chunks' sum.
+// HBM: x read three times, y written once, plus 3 values per chunk.
+// ---------------------------------------------------------------------------
+constexpr int kWideNT = 256;
+constexpr int kWidePer = 8;
+constexpr uint32_t kWideChunk = kWideNT * kWidePer;  // offsets per chunk
+
+struct WideGeom {
+    uint64_t n, w, count;
+    uint64_t nseg;  // segments holding input: ceil(n / w)
+    uint64_t nch;   // chunks per segment: ceil(w / T)
+};
+
+// LDS slot of element e of a chunk: one pad word per eight elements, so that
+// a thread's run of eight (read across lanes) hits distinct banks.
+__device__ __forceinline__ uint32_t wide_slot(uint32_t e) { return e + e / kWidePer; }
+
+// Chunk c of segment a into the thread's run of kWidePer consecutive
+// elements (coalesced loads, turned around in LDS); elements outside the
+// segment or past n read as the identity.
+template <class Op>
+__device__ __forceinline__ void wide_load(const typename Op::T* __restrict__ x, const WideGeom& g,
+                                          uint64_t a, uint64_t c, typename Op::T* buf,
+                                          typename Op::T (&v)[kWidePer]) {
+    using T = typename Op::T;
+    const uint64_t seg0 = a * g.w;
+    const uint64_t off0 = c * kWideChunk;
+#pragma unroll
+    for (int k = 0; k < kWidePer; ++k) {
+        const uint32_t e = (uint32_t)k * kWideNT + threadIdx.x;
+        const uint64_t o = off0 + e;
+        const uint64_t i = seg0 + o;
+        buf[wide_slot(e)] = (o < g.w && i < g.n) ? x[i] : Op::identity();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kWidePer; ++j) v[j] = buf[wide_slot(threadIdx.x * kWidePer + j)];
+    __syncthreads();
+    (void)sizeof(T);
+}
+
+// Workgroup-wide ordered scans of the threads' totals (thread order = element
+// order).  excl: the sum of all earlier threads; after: of all later ones.
+template <class Op>
+__device__ __forceinline__ typename Op::T wide_excl_before(typename Op::T t, typename Op::T* part) {
+    using T = typename Op::T;
+    const int lane = lane_id(), wv = wave_id();
+    T incl = t;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const T o = shfl(incl, lane, -d);
+        if (lane >= d) incl = Op::combine(o, incl);
+    }
+    T before = shfl(incl, lane, -1);
+    if (lane == kWave - 1) part[wv] = incl;
+    __syncthreads();
+    T wpre = Op::identity();
+    for (int q = 0; q < wv; ++q) wpre = Op::combine(wpre, part[q]);
+    before = lane == 0 ? wpre : Op::combine(wpre, before);
+    __syncthreads();
+    return before;
+}
+
+template <class Op>
+__device__ __forceinline__ typename Op::T wide_excl_after(typename Op::T t, typename Op::T* part) {
+    using T = typename Op::T;
+    const int lane = lane_id(), wv = wave_id();
+    T incl = t;  // t (+) the later lanes of the wave
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const T o = shfl(incl, lane, d);
+        if (lane + d < kWave) incl = Op::combine(incl, o);
+    }
+    T after = shfl(incl, lane, 1);
+    if (lane == 0) part[wv] = incl;
+    __syncthreads();
+    T wsuf = Op::identity();
+    for (int q = kWideNT / kWave - 1; q > wv; --q) wsuf = Op::combine(part[q], wsuf);
+    after = lane == kWave - 1 ? wsuf : Op::combine(after, wsuf);
+    __syncthreads();
+    return after;
+}
+
+// 1. sums[a * nch + c] = the sum of chunk c of segment a
+template <class Op>
+__global__ __launch_bounds__(kWideNT) void wide_chunk_sum_kernel(const typename Op::T* __restrict__ x,
+                                                                  WideGeom g,
+                                                                  typename Op::T* __restrict__ sums) {
+    using T = typename Op::T;
+    __shared__ T buf[kWideChunk + kWideChunk / kWidePer];
+    __shared__ T part[kWideNT / kWave];
+    const uint64_t a = blockIdx.x / g.nch, c = blockIdx.x % g.nch;
+    T v[kWidePer];
+    wide_load<Op>(x, g, a, c, buf, v);
+    T t = v[0];
+#pragma unroll
+    for (int j = 1; j < kWidePer; ++j) t = Op::combine(t, v[j]);
+    const T before = wide_excl_before<Op>(t, part);
+    if (threadIdx.x == kWideNT - 1) sums[blockIdx.x] = Op::combine(before, t);
+}
+
+// 2. per segment (one workgroup): pre[a][c] = sum of chunks 0 .. c-1,
+//    post[a][c] = sum of chunks c+1 .. nch-1
+template <class Op>
+__global__ __launch_bounds__(kWideNT) void wide_chunk_scan_kernel(
+    const typename Op::T* __restrict__ sums, WideGeom g, typename Op::T* __restrict__ pre,
+    typename Op::T* __restrict__ post) {
+    using T = typename Op::T;
+    __shared__ T part[kWideNT / kWave];
+    const uint64_t base = (uint64_t)blockIdx.x * g.nch;
+    T carry = Op::identity();
+    for (uint64_t c0 = 0; c0 < g.nch; c0 += kWideNT) {
+        const uint64_t c = c0 + threadIdx.x;
+        const T t = c < g.nch ? sums[base + c] : Op::identity();
+        const T before = wide_excl_before<Op>(t, part);
+        if (c < g.nch) pre[base + c] = Op::combine(carry, before);
+        // the block's total: before (+) t of its last thread
+        __shared__ T total;
+        if (threadIdx.x == kWideNT - 1) total = Op::combine(before, t);
+        __syncthreads();
+        carry = Op::combine(carry, total);
+        __syncthreads();
+    }
+    carry = Op::identity();
+    for (uint64_t e0 = 0; e0 < g.nch; e0 += kWideNT) {
+        // blocks from the end: c = nch - 1 - e0 - (NT - 1 - tid) keeps thread order = chunk order
+        const int64_t c = (int64_t)g.nch - 1 - (int64_t)e0 - (int64_t)(kWideNT - 1 - threadIdx.x);
+        const T t = c >= 0 ? sums[base + (uint64_t)c] : Op::identity();
+        const T after = wide_excl_after<Op>(t, part);
+        if (c >= 0) post[base + (uint64_t)c] = Op::combine(after, carry);
+        __shared__ T total;
+        if (threadIdx.x == 0) total = Op::combine(t, after);
+        __syncthreads();
+        carry = Op::combine(total, carry);
+        __syncthreads();
+    }
+}
+
+// 3. outputs y_{a w + o} for the offsets o of chunk c
+template <class Op>
+__global__ __launch_bounds__(kWideNT) void wide_out_kernel(const typename Op::T* __restrict__ x,
+                                                           WideGeom g,
+                                                           const typename Op::T* __restrict__ pre,
+                                                           const typename Op::T* __restrict__ post,
+                                                           typename Op::T* __restrict__ y) {
+    using T = typename Op::T;
+    __shared__ T buf[kWideChunk + kWideChunk / kWidePer];
+    __shared__ T part[kWideNT / kWave];
+    const uint64_t a = blockIdx.x / g.nch, c = blockIdx.x % g.nch;
+    const uint64_t out0 = a * g.w + c * kWideChunk;  // first output of the chunk
+    if (out0 >= g.count) return;                        // uniform over the workgroup
+    // A's chunk: inclusive suffixes inside the chunk, then the later chunks
+    T va[kWidePer];
+    wide_load<Op>(x, g, a, c, buf, va);
+#pragma unroll
+    for (int j = kWidePer - 2; j >= 0; --j) va[j] = Op::combine(va[j], va[j + 1]);
+    const T after = wide_excl_after<Op>(va[0], part);
+    const T tail = Op::combine(after, post[a * g.nch + c]);
+#pragma unroll
+    for (int j = 0; j < kWidePer; ++j) va[j] = Op::combine(va[j], tail);
+    // B's chunk: exclusive prefixes inside the chunk after the earlier chunks
+    T vb[kWidePer];
+    const bool has_b = a + 1 < g.nseg;
+    if (has_b) {
+        wide_load<Op>(x, g, a + 1, c, buf, vb);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kWidePer; ++j) vb[j] = Op::identity();
+    }
+    T run = vb[0];
+#pragma unroll
+    for (int j = 1; j < kWidePer; ++j) {
+        const T nx = Op::combine(run, vb[j]);
+        vb[j] = run;  // exclusive inside the thread
+        run = nx;
+    }
+    vb[0] = Op::identity();
+    const T before = wide_excl_before<Op>(run, part);
+    const T head = has_b ? Op::combine(pre[(a + 1) * g.nch + c], before) : Op::identity();
+    // y = Sf_A (+) Pf_B, staged through LDS for coalesced stores
+#pragma unroll
+    for (int j = 0; j < kWidePer; ++j)
+        buf[wide_slot(threadIdx.x * kWidePer + j)] = Op::combine(va[j], Op::combine(head, vb[j]));
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kWidePer; ++k) {
+        const uint32_t e = (uint32_t)k * kWideNT + threadIdx.x;
+        const uint64_t o = c * kWideChunk + e;
+        const uint64_t i = a * g.w + o;
+        if (o < g.w && i < g.count) y[i] = buf[wide_slot(e)];
+    }
+}
+
+uint64_t wide_workspace_bytes(int op, uint64_t n, uint64_t w) {
+    const uint64_t esz = op == kOpAffine ? 8 : 4;
+    const uint64_t nseg = (n + w - 1) / w, nch = (w + kWideChunk - 1) / kWideChunk;
+    const uint64_t one = (nseg * nch * esz + 255) & ~255ull;
+    return 3 * one;
+}
+
+template <class Op>
+static int launch_wide_op(const void* x, uint64_t n, uint64_t w, void* y, uint64_t count,
+                          void* workspace, hipStream_t s) {
+    using T = typename Op::T;
+    WideGeom g;
+    g.n = n;
+    g.w = w;
+    g.count = count;
+    g.nseg = (n + w - 1) / w;
+    g.nch = (w + kWideChunk - 1) / kWideChunk;
+    const uint64_t one = (g.nseg * g.nch * sizeof(T) + 255) & ~255ull;
+    T* sums = static_cast<T*>(workspace);
+    T* pre = reinterpret_cast<T*>(static_cast<uint8_t*>(workspace) + one);
+    T* post = reinterpret_cast<T*>(static_cast<uint8_t*>(workspace) + 2 * one);
+    const T* xt = static_cast<const T*>(x);
+    const dim3 grid((unsigned)(g.nseg * g.nch)), block(kWideNT);
+    hipLaunchKernelGGL((wide_chunk_sum_kernel<Op>), grid, block, 0, s, xt, g, sums);
+    hipLaunchKernelGGL((wide_chunk_scan_kernel<Op>), dim3((unsigned)g.nseg), block, 0, s, sums, g,
+                       pre, post);
+    // output chunks: segments that hold an output (a w <= count - 1)
+    const uint64_t nout = (count - 1) / w + 1;
+    hipLaunchKernelGGL((wide_out_kernel<Op>), dim3((unsigned)(nout * g.nch)), block, 0, s, xt, g,
+                       pre, post, static_cast<T*>(y));
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_sliding_wide(int op, const void* x, uint64_t n, uint64_t w, void* y, uint64_t count,
+                        void* workspace, hipStream_t s) {
+    switch (op) {
+    case kOpAdd: return launch_wide_op<OpAdd>(x, n, w, y, count, workspace, s);
+    case kOpMin: return launch_wide_op<OpMin>(x, n, w, y, count, workspace, s);
+    case kOpMax: return launch_wide_op<OpMax>(x, n, w, y, count, workspace, s);
+    case kOpAffine: return launch_wide_op<OpAffine>(x, n, w, y, count, workspace, s);
+    default: return -2;
+    }
+}
+
 int launch_sliding_log(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
                        hipStream_t s) {
     switch (op) {

@@ -23,6 +23,10 @@ int launch_sliding_prefix(int op, const void* x, uint64_t n, uint32_t w, void* y
                           uint64_t count, uint64_t target_waves, hipStream_t s);
 int launch_sliding_log(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
                        hipStream_t s);
+// Windows longer than a slab (any w): chunked segment sums in a workspace.
+uint64_t wide_workspace_bytes(int op, uint64_t n, uint64_t w);
+int launch_sliding_wide(int op, const void* x, uint64_t n, uint64_t w, void* y, uint64_t count,
+                        void* workspace, hipStream_t s);
 
 // genome.hip
 enum { kInAscii = 0, kIn2bit = 1 };

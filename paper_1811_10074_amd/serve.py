@@ -95,6 +95,8 @@ class Request:
     future: concurrent.futures.Future = field(default_factory=concurrent.futures.Future)
     admitted: float = 0.0
     finished: float = 0.0
+    bound: int = -1           # most minimizers the request can have (-1: not counted yet)
+    solo: bool = False        # re-run alone after its batch failed
 
     @property
     def nbases(self) -> int:
@@ -113,8 +115,12 @@ class Result:
 
 
 def window_bound(offsets: np.ndarray, k: int, w: int) -> int:
-    lens = np.diff(np.asarray(offsets, dtype=np.int64))
-    return int(np.maximum(lens - k - w + 2, 0).sum())
+    """Windows of w k-mers over the reads: sum of max(0, len - k - w + 2)."""
+    lens = np.diff(offsets.view(np.int64) if offsets.dtype == np.uint64 else
+                   np.asarray(offsets, dtype=np.int64))
+    c = k + w - 2
+    # every read contributes len - c, the reads shorter than c give back c - len
+    return int(offsets[-1]) - c * lens.size + int(np.maximum(c - lens, 0).sum())
 
 
 class Executor:
@@ -124,6 +130,10 @@ class Executor:
 
     def footprint(self, nbases: int, nreads: int, bound: int) -> int:
         raise NotImplementedError
+
+    def footprint_upper(self, nbases: int, nreads: int, bound: int) -> int:
+        """An upper bound of footprint() that is cheap to evaluate."""
+        return self.footprint(nbases, nreads, bound)
 
     def start(self, reqs: List[Request], slot: int):
         raise NotImplementedError
@@ -153,6 +163,24 @@ def _split(reqs: List[Request], h, p, ro):
     return out
 
 
+def _split_views(reqs: List[Request], h, p, ro):
+    """As _split, with the results as views of the batch's arrays (which the
+    caller owns and does not reuse)."""
+    out = []
+    r0 = 0
+    ro = np.asarray(ro, dtype=np.uint64)
+    for q in reqs:
+        n = q.nreads
+        a, e = int(ro[r0]), int(ro[r0 + n])
+        out.append(Result(h[a:e], p[a:e], ro[r0:r0 + n + 1] - np.uint64(a)))
+        r0 += n
+    return out
+
+
+# Host copies are cut into pieces of this many bytes for the copy pool.
+_COPY_PIECE = 4 << 20
+
+
 def _concat(reqs: List[Request]):
     nreads = sum(q.nreads for q in reqs)
     off = np.zeros(nreads + 1, dtype=np.uint64)
@@ -177,7 +205,7 @@ class GPUExecutor(Executor):
 
     def __init__(self, k: int, w: int, arena_bytes: Optional[int] = None,
                  streams: Optional[int] = None, canonical: bool = True, hashed: bool = True,
-                 device: str = "cuda"):
+                 device: str = "cuda", copy_threads: int = 8):
         import torch
         if streams is None:
             # one stream per hardware queue besides torch's default stream:
@@ -201,6 +229,12 @@ class GPUExecutor(Executor):
         self.staging = [None] * streams
         self.out_staging = [None] * streams
         self.lib = _lib.load()
+        # host copies (packing into pinned staging, results out of it) run on
+        # a small pool: numpy copies release the interpreter lock, and one
+        # thread's memcpy bandwidth bounds a large batch otherwise
+        self.copy_threads = max(1, min(copy_threads, len(os.sched_getaffinity(0))))
+        self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=self.copy_threads,
+                                                          thread_name_prefix="sws-copy")
 
     def prepare(self, staging_bytes: int):
         """Before requests arrive: allocate every stream's pinned input and
@@ -220,7 +254,8 @@ class GPUExecutor(Executor):
         # use yet): the same copies and library launches as a real batch
         tiny = Request(-1, np.frombuffer(b"ACGT" * 16, dtype=np.uint8).copy(),
                        np.array([0, 64], dtype=np.uint64), 0.0)
-        need = self.footprint(64, 1, window_bound(tiny.offsets, self.k, self.w))
+        tiny.bound = window_bound(tiny.offsets, self.k, self.w)
+        need = self.footprint(64, 1, tiny.bound)
         if need * len(self.streams) > self.arena_bytes():
             return
         handles = [self.start([tiny], i * need) for i in range(len(self.streams))]
@@ -266,6 +301,13 @@ class GPUExecutor(Executor):
     def footprint(self, nbases, nreads, bound):
         return self._layout(nbases, nreads, bound)[1]
 
+    def footprint_upper(self, nbases, nreads, bound):
+        # bases; two offset arrays; hash, pos and read per window; the
+        # workspace (256 bytes plus 68 per tile of at least 512 windows for
+        # w <= 32); 256 bytes of rounding for each of the seven parts
+        return (nbases + 16 * (nreads + 1) + 16 * bound + 256 + 68 * (nbases // 512 + 2)
+                + 7 * Arena.ALIGN)
+
     def start(self, reqs, slot):
         torch = self.torch
         nreads = sum(q.nreads for q in reqs)
@@ -282,13 +324,30 @@ class GPUExecutor(Executor):
         pin_np = pin.numpy()
         off = pin_np[ob:ob + 8 * (nreads + 1)].view(np.uint64)
         off[0] = 0
+        # copy jobs of about _COPY_PIECE bytes each: a large request is cut
+        # into pieces, small ones share a job
+        jobs, cur, cur_bytes = [], [], 0
         b0, r0 = 0, 0
         for q in reqs:
-            pin_np[b0:b0 + q.nbases] = q.seqs
             np.add(q.offsets[1:], np.uint64(b0), out=off[r0 + 1:r0 + q.nreads + 1])
+            for x0 in range(0, q.nbases, _COPY_PIECE):
+                x1 = min(q.nbases, x0 + _COPY_PIECE)
+                cur.append((b0 + x0, q.seqs, x0, x1))
+                cur_bytes += x1 - x0
+                if cur_bytes >= _COPY_PIECE:
+                    jobs.append(cur)
+                    cur, cur_bytes = [], 0
             b0 += q.nbases
             r0 += q.nreads
-        bound = window_bound(off, self.k, self.w)
+        if cur:
+            jobs.append(cur)
+
+        def pack(job):
+            for d0, src, x0, x1 in job:
+                pin_np[d0:d0 + x1 - x0] = src[x0:x1]
+
+        self._parallel(pack, jobs)
+        bound = sum(q.bound for q in reqs)
         lay, _ = self._layout(nbases, nreads, bound)
 
         def view(name, dtype, count):
@@ -337,7 +396,15 @@ class GPUExecutor(Executor):
         handle["event"].synchronize()
         lay, slot, nreads = handle["lay"], handle["slot"], handle["nreads"]
         stream = self.streams[handle["stream"]]
-        self.free_streams.append(handle["stream"])
+        try:
+            return self._finish(handle, lay, slot, nreads, stream)
+        finally:
+            # the stream (and its pinned buffers) serve the next batch only
+            # once this batch's results are out of them
+            self.free_streams.append(handle["stream"])
+
+    def _finish(self, handle, lay, slot, nreads, stream):
+        torch = self.torch
 
         def dev(name, count, dtype):
             o, _n = lay[name]
@@ -368,7 +435,29 @@ class GPUExecutor(Executor):
             o = out.numpy()
             h = o[:8 * total].view(np.uint64)
             p = o[8 * total:12 * total].view(np.uint32)
-        return _split(handle["reqs"], h, p, ro)  # copies out of the pinned buffer
+        # one copy of the batch's results out of the pinned buffer (which the
+        # stream's next batch reuses), in pieces on the copy pool; each
+        # request's result is a view of it
+        hb = np.empty(total, dtype=np.uint64)
+        pb = np.empty(total, dtype=np.uint32)
+        pieces = [(a, min(total, a + _COPY_PIECE // 8)) for a in range(0, total, _COPY_PIECE // 8)]
+
+        def copy_piece(ab):
+            a, e = ab
+            hb[a:e] = h[a:e]
+            pb[a:e] = p[a:e]
+
+        self._parallel(copy_piece, pieces)
+        return _split_views(handle["reqs"], hb, pb, ro)
+
+    def _parallel(self, fn, items):
+        """fn over items on the copy pool (inline when there is one item)."""
+        if len(items) <= 1 or self.copy_threads == 1:
+            for it in items:
+                fn(it)
+            return
+        for f in [self.pool.submit(fn, it) for it in items]:
+            f.result()
 
 
 # ---------------------------------------------------------------------------
@@ -447,11 +536,15 @@ class Server:
         self.max_batch_bases = max_batch_bases
         self.poll_s = poll_s
         self.queue = collections.deque()
-        self.lock = threading.Lock()
+        self.lock = threading.Lock()        # the queue
+        self.state_lock = threading.Lock()  # the arena and the in-flight list
         self.wake = threading.Event()
-        self.inflight = []  # (handle, slot, nbytes, reqs)
+        self.inflight = []  # [handle, slot, nbytes, reqs, handed to the completer]
+        self.done_q = collections.deque()
+        self.done_wake = threading.Event()
         self.stop_flag = False
         self.thread = None
+        self.completer = None
         self.next_id = 0
         self.completed: List[Request] = []
 
@@ -461,7 +554,15 @@ class Server:
         q = Request(self.next_id, np.ascontiguousarray(seqs, dtype=np.uint8), off,
                     time.perf_counter() if arrival is None else arrival)
         self.next_id += 1
-        need = self.ex.footprint(q.nbases, q.nreads, window_bound(off, self.k, self.w))
+        # the oversize check with cheap upper bounds first (at most one window
+        # per base past the first k + w - 2); the exact window count and
+        # footprint only when those do not fit.  Otherwise the scheduler thread
+        # counts the windows, off the client's path
+        cheap = self.ex.footprint_upper(q.nbases, q.nreads, max(0, q.nbases - self.k - self.w + 2))
+        need = cheap
+        if cheap > self.arena.size:
+            q.bound = window_bound(off, self.k, self.w)
+            need = self.ex.footprint(q.nbases, q.nreads, q.bound)
         if need > self.arena.size:
             q.future.set_exception(RequestTooLarge(
                 "request needs %d arena bytes, the arena has %d" % (need, self.arena.size)))
@@ -482,7 +583,10 @@ class Server:
             prepare(Arena.round(min(self.max_batch_bases, self.arena.size)) +
                     8 * (min(self.max_batch_bases, 1 << 20) + 1))
         self.thread = threading.Thread(target=self._loop, name="sws-scheduler", daemon=True)
+        self.completer = threading.Thread(target=self._complete_loop, name="sws-completer",
+                                          daemon=True)
         self.thread.start()
+        self.completer.start()
         return self
 
     def stop(self, drain: bool = True, timeout: float = 60.0):
@@ -492,55 +596,57 @@ class Server:
                 time.sleep(0.001)
         self.stop_flag = True
         self.wake.set()
+        self.done_wake.set()
         if self.thread:
             self.thread.join(timeout)
+        if self.completer:
+            self.completer.join(timeout)
 
     # -- scheduler ----------------------------------------------------------
     def _form_batch(self):
-        """Oldest-first requests that fit together in free arena bytes."""
+        """Oldest-first requests that fit together in free arena bytes.  A
+        request re-run after its batch failed forms a batch alone."""
         reqs, nb, nr, bound = [], 0, 0, 0
-        with self.lock:
+        with self.lock, self.state_lock:
             while self.queue:
                 q = self.queue[0]
-                b2 = bound + window_bound(q.offsets, self.k, self.w)
-                need = self.ex.footprint(nb + q.nbases, nr + q.nreads, b2)
+                if reqs and (q.solo or reqs[0].solo):
+                    break
+                if q.bound < 0:
+                    q.bound = window_bound(q.offsets, self.k, self.w)
+                b2 = bound + q.bound
+                # the cheap upper bound for the fit test; the exact footprint
+                # (never larger) sizes the allocation below
+                need = self.ex.footprint_upper(nb + q.nbases, nr + q.nreads, b2)
                 if reqs and nb + q.nbases > self.max_batch_bases:
                     break
                 if need > self.arena.free_bytes:
                     break
                 reqs.append(self.queue.popleft())
                 nb, nr, bound = nb + q.nbases, nr + q.nreads, b2
-        if not reqs:
-            return None
-        need = self.ex.footprint(nb, nr, bound)
-        slot = self.arena.alloc(need)
-        if slot is None:  # fragmented: put them back, retry after a completion
-            with self.lock:
+            if not reqs:
+                return None
+            need = self.ex.footprint(nb, nr, bound)
+            slot = self.arena.alloc(need)
+            if slot is None:  # fragmented: put them back, retry after a completion
                 self.queue.extendleft(reversed(reqs))
-            return None
+                return None
         return reqs, slot, need
 
     def _loop(self):
+        """Scheduler: hands finished batches to the completer and admits new
+        ones while streams and arena bytes allow."""
         while not self.stop_flag:
             progressed = False
-            # completions
-            for item in list(self.inflight):
-                handle, slot, nbytes, reqs = item
-                if self.ex.done(handle):
-                    self.inflight.remove(item)
-                    try:
-                        results = self.ex.finish(handle)
-                        now = time.perf_counter()
-                        for q, r in zip(reqs, results):
-                            q.finished = now
-                            q.future.set_result(r)
-                    except Exception as exc:  # the batch failed: isolate per request
-                        self._retry_alone(reqs, exc)
-                    self.arena.release(slot, nbytes)
-                    self.completed.extend(reqs)
-                    progressed = True
-            # admissions
-            while len(self.inflight) < self.ex.slots() and self.queue:
+            with self.state_lock:
+                for item in self.inflight:
+                    if not item[4] and self.ex.done(item[0]):
+                        item[4] = True
+                        self.done_q.append(item)
+                        self.done_wake.set()
+                        progressed = True
+                busy = len(self.inflight)
+            while busy < self.ex.slots() and self.queue:
                 b = self._form_batch()
                 if b is None:
                     break
@@ -551,11 +657,14 @@ class Server:
                 try:
                     handle = self.ex.start(reqs, slot)
                 except Exception as exc:
-                    self.arena.release(slot, need)
+                    with self.state_lock:
+                        self.arena.release(slot, need)
                     for q in reqs:
                         q.future.set_exception(exc)
                     continue
-                self.inflight.append((handle, slot, need, reqs))
+                with self.state_lock:
+                    self.inflight.append([handle, slot, need, reqs, False])
+                busy += 1
                 progressed = True
             if not progressed:
                 if not self.inflight and not self.queue:
@@ -564,29 +673,44 @@ class Server:
                 else:
                     time.sleep(self.poll_s)
 
-    def _retry_alone(self, reqs, exc):
-        """A failed batch is re-run one request at a time, so one bad request
-        fails alone."""
-        if len(reqs) == 1:
-            reqs[0].future.set_exception(exc)
-            return
-        for q in reqs:
-            need = self.ex.footprint(q.nbases, q.nreads, window_bound(q.offsets, self.k, self.w))
-            slot = self.arena.alloc(need)
-            if slot is None:
-                q.future.set_exception(exc)
+    def _complete_loop(self):
+        """Completer: collects a finished batch's results (the host copies run
+        here, beside the scheduler's packing of the next batch), resolves the
+        futures and frees the batch's arena bytes.  A failed batch's requests
+        go back to the front of the queue to be re-run one by one, so that a
+        bad request fails alone."""
+        while True:
+            if not self.done_q:
+                if self.stop_flag and not self.inflight:
+                    return
+                self.done_wake.wait(0.01)
+                self.done_wake.clear()
                 continue
+            item = self.done_q.popleft()
+            handle, slot, nbytes, reqs, _ = item
+            retry = []
             try:
-                h = self.ex.start([q], slot)
-                while not self.ex.done(h):
-                    time.sleep(self.poll_s)
-                r = self.ex.finish(h)[0]
-                q.finished = time.perf_counter()
-                q.future.set_result(r)
-            except Exception as e2:
-                q.future.set_exception(e2)
-            finally:
-                self.arena.release(slot, need)
+                results = self.ex.finish(handle)
+                now = time.perf_counter()
+                for q, r in zip(reqs, results):
+                    q.finished = now
+                    q.future.set_result(r)
+            except Exception as exc:
+                if len(reqs) == 1:
+                    reqs[0].future.set_exception(exc)
+                else:
+                    for q in reqs:
+                        q.solo = True
+                    retry = reqs
+            with self.state_lock:
+                self.arena.release(slot, nbytes)
+                self.inflight.remove(item)
+                if not retry:
+                    self.completed.extend(reqs)
+            if retry:
+                with self.lock:
+                    self.queue.extendleft(reversed(retry))
+            self.wake.set()
 
 
 def latency_stats(reqs: List[Request]):

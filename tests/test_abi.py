@@ -25,7 +25,7 @@ def test_exports_every_header_function(lib):
 
 
 def test_version_and_status(lib):
-    assert lib.sws_abi_version() == 3
+    assert lib.sws_abi_version() == 4
     for st in (0, -1, -2, -3, -4, -5):
         assert lib.sws_status_str(st)
     assert b"unknown" in lib.sws_status_str(7)
@@ -164,3 +164,37 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
                        cwd=str(__import__("pathlib").Path(__file__).resolve().parents[1]))
     assert r.returncode == 0 and "raised: True" in r.stdout, r.stdout + r.stderr
+
+
+def test_wide_window_validation(lib):
+    """Windows above 2048 need the workspace call; validation happens on the
+    host before anything is enqueued."""
+    s = NULL
+    b = ctypes.c_uint64(0)
+    # no scratch for short windows or for paths that keep their own limits
+    assert lib.sws_sliding_sum_workspace(0, 2048, 1 << 20, 0, ctypes.byref(b)) == _lib.SWS_OK
+    assert b.value == 0
+    assert lib.sws_sliding_sum_workspace(1, 5000, 1 << 20, 2, ctypes.byref(b)) == _lib.SWS_OK
+    assert b.value == 0
+    assert lib.sws_sliding_sum_workspace(1, 5000, 100, 0, ctypes.byref(b)) == _lib.SWS_OK
+    assert b.value == 0  # n < w: no outputs
+    # 3 values per chunk of 2048 offsets per segment
+    assert lib.sws_sliding_sum_workspace(0, 65537, 1 << 20, 0, ctypes.byref(b)) == _lib.SWS_OK
+    nseg, nch = -(-(1 << 20) // 65537), -(-65537 // 2048)
+    assert b.value >= 3 * nseg * nch * 4
+    assert lib.sws_sliding_sum_workspace(3, 65537, 1 << 20, 1, ctypes.byref(b)) == _lib.SWS_OK
+    assert b.value >= 3 * nseg * nch * 8
+    assert lib.sws_sliding_sum_workspace(9, 65537, 1 << 20, 0, ctypes.byref(b)) == _lib.SWS_ERR_INVALID
+    assert lib.sws_sliding_sum_workspace(0, 0, 1 << 20, 0, ctypes.byref(b)) == _lib.SWS_ERR_INVALID
+    # the short-window entry point still refuses wide windows
+    assert lib.sws_sliding_sum(0, 4097, FAKE, 1 << 20, FAKE, s) == _lib.SWS_ERR_UNSUPPORTED
+    # the wide call: workspace missing or small, explicit paths past their limits
+    ws = ctypes.c_uint64(0)
+    assert lib.sws_sliding_sum_workspace(0, 4097, 1 << 20, 0, ctypes.byref(ws)) == _lib.SWS_OK
+    assert lib.sws_sliding_sum_ws(0, 4097, FAKE, 1 << 20, FAKE, 0, NULL, ws.value, s) == _lib.SWS_ERR_WORKSPACE
+    assert lib.sws_sliding_sum_ws(0, 4097, FAKE, 1 << 20, FAKE, 0, FAKE, ws.value - 1, s) == _lib.SWS_ERR_WORKSPACE
+    assert lib.sws_sliding_sum_ws(0, 4097, FAKE, 1 << 20, FAKE, 3, FAKE, ws.value, s) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_sliding_sum_ws(1, 5000, FAKE, 1 << 20, FAKE, 2, FAKE, ws.value, s) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_sliding_sum_ws(0, 4097, FAKE, 1 << 20, FAKE, 4, FAKE, ws.value, s) == _lib.SWS_ERR_UNSUPPORTED
+    assert lib.sws_sliding_sum_ws(3, 4097, ctypes.c_void_p(0x10004), 1 << 20, FAKE, 0, FAKE, 1 << 30, s) == _lib.SWS_ERR_INVALID
+    assert lib.sws_sliding_sum_ws(0, 4097, NULL, 100, NULL, 0, NULL, 0, s) == _lib.SWS_OK  # n < w

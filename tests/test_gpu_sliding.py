@@ -285,3 +285,64 @@ def test_beyond_2p32_elements_sampled(op):
             del y
     del t
     torch.cuda.empty_cache()
+
+
+def _wide_expected(op, w, x):
+    """O(N) expectations: the deque (min, max), the prefix identity (+), the
+    prefix compositions (affine with odd multipliers)."""
+    if op in ("min", "max"):
+        return oracle.sliding_extremum_deque(op, w, x)
+    if op == "affine":
+        return oracle.affine_windows_by_prefix(w, x)
+    pfx = np.zeros(x.size + 1, dtype=np.uint64)
+    np.cumsum(x, dtype=np.uint64, out=pfx[1:])
+    return ((pfx[w:] - pfx[:-w]) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+@pytest.mark.parametrize("op", ["add", "min", "max", "affine"])
+def test_wide_windows(op):
+    """Windows past one slab (Eq. 2 holds for every w): w in {2049, 4097,
+    65537} and a window of 2^22 + 3, with n from exactly w (one output) to
+    several segments with a ragged last chunk; every output against an O(N)
+    oracle and sampled outputs against the fold itself, on AUTO and GENERIC."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    rng = np.random.default_rng({"add": 1, "min": 2, "max": 3, "affine": 4}[op])
+    cases = [(2049, 2049), (2049, 2050), (2049, 3 * 2049 + 777), (4097, 100_003),
+             (65537, 65537 + 1), (65537, 1_000_000), (65537, 1 << 22), ((1 << 22) + 3, 1 << 24)]
+    for w, n in cases:
+        print("wide window: op=%s w=%d n=%d" % (op, w, n), flush=True)
+        x = inputs.affine_pairs(n, seed=w % 1000, odd=True) if op == "affine" else \
+            inputs.uniform_u32(n, seed=w % 1000)
+        if op in ("min", "max") and n > 5000:
+            x[rng.integers(0, n, 50)] = 0 if op == "min" else 0xFFFFFFFF  # extremes to carry far
+        exp = _wide_expected(op, w, x)
+        t = dev(x, torch)
+        for path in ("auto", "generic"):
+            y = sws.sliding_sum(op, w, t, path=path)
+            torch.cuda.synchronize()
+            got = host_u32(y)
+            assert got.shape == exp.shape, (op, w, n, path)
+            if not np.array_equal(got, exp):
+                bad = np.nonzero(got.reshape(len(got), -1) != exp.reshape(len(exp), -1))[0]
+                raise AssertionError("op=%s w=%d n=%d path=%s: %d mismatches, first at %d"
+                                     % (op, w, n, path, bad.size, bad[0]))
+        if w <= 65537:
+            idx = np.concatenate([[0, exp.shape[0] - 1], rng.integers(0, exp.shape[0], 5)])
+            for i in idx:
+                assert np.array_equal(exp[i], oracle.sliding_sum(op, w, x[i:i + w])[0]), (op, w, i)
+
+
+def test_wide_windows_beyond_other_paths():
+    """LOG serves min and max up to 4096 only; PREFIX (+) and SCALAR keep
+    their limits; n < w gives no outputs."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    x = dev(inputs.uniform_u32(10_000, seed=5), torch)
+    with pytest.raises(ValueError):
+        sws.sliding_sum("min", 4097, x, path="log")
+    with pytest.raises(ValueError):
+        sws.sliding_sum("add", 4097, x, path="prefix")
+    with pytest.raises(ValueError):
+        sws.sliding_sum("add", 4097, x, path="scalar")
+    assert sws.sliding_sum("max", 10_001, x).numel() == 0
