@@ -361,7 +361,8 @@ int sws_seed_table(const uint64_t *hash, const uint32_t *pos, uint64_t count, ui
  * sliding-sum launch aims for.  The input is cut into slabs of 64*R elements
  * (R = 8, 16 or 32 by window and operator) and each wavefront streams
  * ceil(slabs / waves) consecutive slabs, so fewer waves means longer streams
- * per wave.  0 restores the default (32768: 128 per compute unit).  Results
+ * per wave.  0 restores the default (32768, 128 per compute unit; 65536 for
+ * AFFINE with w <= 512).  Results
  * do not depend on it.  The setting belongs to the
  * calling thread: it applies to that thread's later calls only.
  * Errors: SWS_ERR_INVALID (waves > 2^24).

@@ -1017,6 +1017,12 @@ __global__ __launch_bounds__(NT, IN == kIn2bit ? 5 : 1) void minimizer_wave_kern
 // ---------------------------------------------------------------------------
 constexpr int kTileRange = kWaveKeys + 64;   // positions whose boundaries a tile needs
 constexpr int kBitmapWords = kTileRange / 32 + 2;
+// Reads a tile keeps in its LDS table (id, start); a tile overlapping more
+// (reads shorter than about 9 bases on average) finds the rest by a binary
+// search over the offsets.
+constexpr uint32_t kReadSlots = 128;
+// Outputs per round of the batched kernel's store compaction.
+constexpr uint32_t kBatchStage = 384;
 
 // Read containing the first base of each tile: a read covering tiles whose
 // first base (q * tw - 16, clamped at 0) lies in it writes its index there.
@@ -1039,11 +1045,14 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     constexpr int NWV = NT / kWave;
     __shared__ uint32_t s_code[NWV][kWaveWords], s_inv[NWV][kWaveWords];
     __shared__ uint32_t s_bits[NWV][kBitmapWords];
-    __shared__ uint32_t s_rid[NWV][kTileRange + 1];
-    __shared__ uint32_t s_rstart[NWV][kTileRange + 1];
+    __shared__ uint32_t s_rid[NWV][kReadSlots];
+    __shared__ uint32_t s_rstart[NWV][kReadSlots];
     __shared__ uint32_t s_lexcl[NWV][kWave], s_lemit[NWV][kWave];
     __shared__ uint32_t s_cnt[NWV];  // stores per wave tile
     __shared__ uint64_t s_base;      // stores before the workgroup
+    __shared__ uint64_t s_stage_hash[NWV][kBatchStage];
+    __shared__ uint32_t s_stage_pos[NWV][kBatchStage];
+    __shared__ uint32_t s_stage_read[NWV][kBatchStage];
 
     const int lane = lane_id();
     const int wv = wave_id();
@@ -1061,6 +1070,7 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     const int64_t p0 = (int64_t)(cur * a.tw);
     const int64_t K0 = p0 - 16;
     uint32_t r0 = 0, pre = 0, emit = 0, cnt = 0, incl = 0, sincl = 0, starts = 0;
+    uint32_t nlisted = 0;  // reads the tile overlaps (the table keeps kReadSlots)
     uint32_t wbad = 0;   // split semantics: windows holding an invalid k-mer
     uint32_t wnone = 0;  // windows without a valid k-mer (FULL = false)
     uint64_t B = 0;
@@ -1084,7 +1094,7 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
             const uint64_t tmask = __ballot(take);
             if (take) {
                 const uint32_t idx = listed + (uint32_t)__builtin_popcountll(tmask & ((1ull << lane) - 1ull));
-                if (idx <= (uint32_t)kTileRange) {
+                if (idx < kReadSlots) {
                     rid[idx] = (uint32_t)r;
                     rstart[idx] = (uint32_t)rs;
                 }
@@ -1099,6 +1109,7 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
             if (__ballot(!have || rs >= rng_end)) break;
         }
         pre = __ballot(pre != 0) ? 1u : 0u;
+        nlisted = listed;
         if (lane == 0 && (int64_t)a.total >= K0 && (int64_t)a.total < rng_end) {
             const uint32_t b = (uint32_t)((int64_t)a.total - K0);  // end of the last read
             atomicOr(&bits[b >> 5], 1u << (b & 31));
@@ -1211,22 +1222,60 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     for (int v = 0; v < wv; ++v) excl += s_cnt[v];
     // read rank of position e: listed reads starting at or before it, minus one
     const int32_t rank0 = (int32_t)(pre + sincl - starts) - 1;
-    uint64_t g = excl + (incl - cnt);
+    // Compaction through wave-private LDS, as in minimizer_wave_kernel: lane
+    // l writes its outputs at their ranks within the wave, then consecutive
+    // lanes store consecutive outputs.  More than kBatchStage outputs take
+    // several rounds.
+    const uint32_t total_w = lane_value(incl, kWave - 1);
+    uint32_t lim = total_w;  // outputs past the capacity are dropped
+    if (excl + total_w > a.capacity) lim = excl >= a.capacity ? 0u : (uint32_t)(a.capacity - excl);
+    uint64_t* sh = s_stage_hash[wv];
+    uint32_t* sp = s_stage_pos[wv];
+    uint32_t* sr = s_stage_read[wv];
+    for (uint32_t c = 0; c < lim; c += kBatchStage) {
+        // stage each output's hash, absolute position and read rank (the
+        // lanes' runs stay in registers: only unrolled loops touch them)
+        uint32_t j = incl - cnt - c;  // rank - c, mod 2^32
 #pragma unroll
-    for (int e = 0; e < kR; ++e) {
-        if ((emit >> e) & 1u) {
-            if (g < a.capacity) {
-                const int32_t rk = rank0 + __builtin_popcountll(B & ((2ull << e) - 1ull));
-                const uint32_t rr = rid[rk];
-                a.out_hash[g] = ((uint64_t)m[e].hi << 32) | m[e].lo;
-                a.out_pos[g] = (uint32_t)(K0 + (int64_t)(m[e].tag & (FULL ? 0x7FFFu : 0xFFFFu))) -
-                               rstart[rk];
-                a.out_read[g] = rr;
+        for (int e = 0; e < kR; ++e) {
+            if ((emit >> e) & 1u) {
+                if (j < kBatchStage) {
+                    sh[j] = ((uint64_t)m[e].hi << 32) | m[e].lo;
+                    sp[j] = (uint32_t)(K0 + (int64_t)(m[e].tag & (FULL ? 0x7FFFu : 0xFFFFu)));
+                    sr[j] = (uint32_t)(rank0 + __builtin_popcountll(B & ((2ull << e) - 1ull)));
+                }
+                ++j;
             }
-            ++g;
         }
+        wave_lds_sync();
+        // resolve ranks to reads and store, consecutive lanes on consecutive
+        // outputs
+        const uint32_t nc = min(kBatchStage, lim - c);
+        for (uint32_t q = (uint32_t)lane; q < nc; q += kWave) {
+            const uint32_t pos = sp[q], rk = sr[q];
+            uint32_t rr, rs;
+            if (rk < kReadSlots && rk < nlisted) {
+                rr = rid[rk];
+                rs = rstart[rk];
+            } else {
+                // past the table: the read holding pos is the last one
+                // starting at or before it (offsets[r0] <= the tile's first
+                // base <= pos < total)
+                uint64_t lo = r0, hi = a.nreads;  // offsets[lo] <= pos < offsets[hi]
+                while (hi - lo > 1) {
+                    const uint64_t mid = lo + (hi - lo) / 2;
+                    if (a.offsets[mid] <= (uint64_t)pos) lo = mid;
+                    else hi = mid;
+                }
+                rr = (uint32_t)lo;
+                rs = (uint32_t)a.offsets[lo];
+            }
+            a.out_hash[excl + c + q] = sh[q];
+            a.out_pos[excl + c + q] = pos - rs;
+            a.out_read[excl + c + q] = rr;
+        }
+        wave_lds_sync();
     }
-    wave_lds_sync();
     // output offsets of the reads that start in the windows this tile owns
     const bool last = cur == a.ntiles - 1;
     const int64_t own_end = last ? INT64_MAX : p0 + (int64_t)a.tw;

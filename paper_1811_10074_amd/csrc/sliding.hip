@@ -876,6 +876,12 @@ uint32_t log_max_window() { return 4096; }
 
 int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
                            uint64_t tw, hipStream_t s) {
+    // Default wave counts, measured at n = 2^28: 32768 for the 4-byte
+    // operators (fewer, longer streams lose more to the last partial round of
+    // waves than they save on halos); AFFINE with w <= 512 (8-element lane
+    // runs, more waves resident) 65536: 0.72 of HBM peak at w = 4 .. 64 and
+    // 0.71 at w = 256, against 0.68 and 0.67 with 32768.
+    if (tw == 0) tw = (op == kOpAffine && w <= 512u) ? 2 * kDefaultSlidingWaves : kDefaultSlidingWaves;
     // <Op, R, waves per workgroup>
     const bool big = w > (uint32_t)(kWave * 16);
     switch (op) {

@@ -205,7 +205,7 @@ class GPUExecutor(Executor):
 
     def __init__(self, k: int, w: int, arena_bytes: Optional[int] = None,
                  streams: Optional[int] = None, canonical: bool = True, hashed: bool = True,
-                 device: str = "cuda", copy_threads: int = 8):
+                 device: str = "cuda", copy_threads: int = 6):
         import torch
         if streams is None:
             # one stream per hardware queue besides torch's default stream:
@@ -233,8 +233,12 @@ class GPUExecutor(Executor):
         # a small pool: numpy copies release the interpreter lock, and one
         # thread's memcpy bandwidth bounds a large batch otherwise
         self.copy_threads = max(1, min(copy_threads, len(os.sched_getaffinity(0))))
+        # packing and result copies on pools of their own: a batch's results
+        # never wait behind the next batch's packing
         self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=self.copy_threads,
-                                                          thread_name_prefix="sws-copy")
+                                                          thread_name_prefix="sws-pack")
+        self.out_pool = concurrent.futures.ThreadPoolExecutor(max_workers=self.copy_threads,
+                                                              thread_name_prefix="sws-unpack")
 
     def prepare(self, staging_bytes: int):
         """Before requests arrive: allocate every stream's pinned input and
@@ -447,16 +451,17 @@ class GPUExecutor(Executor):
             hb[a:e] = h[a:e]
             pb[a:e] = p[a:e]
 
-        self._parallel(copy_piece, pieces)
+        self._parallel(copy_piece, pieces, self.out_pool)
         return _split_views(handle["reqs"], hb, pb, ro)
 
-    def _parallel(self, fn, items):
-        """fn over items on the copy pool (inline when there is one item)."""
+    def _parallel(self, fn, items, pool=None):
+        """fn over items on a copy pool (inline when there is one item)."""
         if len(items) <= 1 or self.copy_threads == 1:
             for it in items:
                 fn(it)
             return
-        for f in [self.pool.submit(fn, it) for it in items]:
+        pool = pool or self.pool
+        for f in [pool.submit(fn, it) for it in items]:
             f.result()
 
 
@@ -528,8 +533,15 @@ class Server:
     are scanned."""
 
     def __init__(self, executor: Executor, k: int, w: int, max_batch_bases: int = 64 << 20,
-                 poll_s: float = 50e-6, freeze_gc: bool = True):
+                 poll_s: float = 50e-6, freeze_gc: bool = True,
+                 concurrent_bases: int = 16 << 20):
         self.freeze_gc = freeze_gc
+        # a batch starts beside one already running only when at least this
+        # many bases wait: under light load one batch at a time finishes
+        # soonest (concurrent batches share the host copies and the link),
+        # under load all streams stay busy
+        self.concurrent_bases = concurrent_bases
+        self.queued_bases = 0
         self.ex = executor
         self.k, self.w = k, w
         self.arena = Arena(executor.arena_bytes())
@@ -569,6 +581,7 @@ class Server:
             return q.future
         with self.lock:
             self.queue.append(q)
+            self.queued_bases += q.nbases
         self.wake.set()
         return q.future
 
@@ -631,6 +644,7 @@ class Server:
             if slot is None:  # fragmented: put them back, retry after a completion
                 self.queue.extendleft(reversed(reqs))
                 return None
+            self.queued_bases -= nb
         return reqs, slot, need
 
     def _loop(self):
@@ -647,6 +661,8 @@ class Server:
                         progressed = True
                 busy = len(self.inflight)
             while busy < self.ex.slots() and self.queue:
+                if busy > 0 and self.queued_bases < self.concurrent_bases:
+                    break
                 b = self._form_batch()
                 if b is None:
                     break
@@ -710,6 +726,7 @@ class Server:
             if retry:
                 with self.lock:
                     self.queue.extendleft(reversed(retry))
+                    self.queued_bases += sum(q.nbases for q in retry)
             self.wake.set()
 
 

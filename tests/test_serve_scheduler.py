@@ -65,7 +65,7 @@ def test_results_alone_equal_mix():
     srv.stop()
     # mixed: all at once, batched together, several in flight
     ex = FakeExecutor(K, W, slots=3, compute=oracle_compute, latency=lambda rs: 0.005)
-    srv = Server(ex, K, W, max_batch_bases=20_000).start()
+    srv = Server(ex, K, W, max_batch_bases=20_000, concurrent_bases=0).start()
     futs = [srv.submit(*r) for r in reqs]
     mixed = [f.result(timeout=30) for f in futs]
     srv.stop()
@@ -133,3 +133,19 @@ def test_latency_stats():
     srv.stop()
     st = latency_stats(srv.completed)
     assert st["n"] == 10 and st["p99_ms"] >= st["p50_ms"] >= 3.0
+
+
+def test_concurrency_follows_the_queue():
+    """A second batch runs beside the first only when enough bases wait: with
+    a threshold above the whole workload, batches never overlap; with one
+    below it they do."""
+    reqs = [make_request(600 + s) for s in range(30)]
+    total = sum(int(o[-1]) for _, o in reqs)
+    for thr, overlap in ((10 * total, False), (1, True)):
+        ex = FakeExecutor(K, W, slots=3, compute=oracle_compute, latency=lambda rs: 0.004)
+        srv = Server(ex, K, W, max_batch_bases=5_000, concurrent_bases=thr).start()
+        futs = [srv.submit(*r) for r in reqs]
+        res = [f.result(timeout=30) for f in futs]
+        srv.stop()
+        assert all(same(r, expected(*q)) for r, q in zip(res, reqs))
+        assert (ex.max_inflight_seen >= 2) == overlap, (thr, ex.max_inflight_seen)
