@@ -27,8 +27,8 @@ constexpr uint32_t kBlockThreads = 256;
 constexpr uint32_t kBatchDefaultThreads = 256;
 
 // Tiles of a single-sequence call: the same tile width the launch uses.
-uint64_t max_tiles(uint64_t nwin, uint32_t w) {
-    const uint32_t tw = sws::minimizer_windows_per_tile(kBlockThreads, w);
+uint64_t max_tiles(uint64_t nwin, uint32_t k, uint32_t w) {
+    const uint32_t tw = sws::minimizer_windows_per_tile(kBlockThreads, k, w);
     if (tw == 0) return 0;
     return (nwin + tw - 1) / tw;
 }
@@ -70,8 +70,8 @@ int minimizers_common(const sws::GenomeInput& in, uint64_t n, uint32_t k, uint32
     const int st = check_minimizer_call(n, k, w, flags, out_hash, out_pos, capacity, d_count);
     if (st != SWS_OK) return st;
     const uint64_t nwin = window_count(n, k, w);
-    const uint32_t tw = sws::minimizer_windows_per_tile(kBlockThreads, w);
-    if (tw == 0) return SWS_ERR_UNSUPPORTED;  // unreachable for w <= 1024
+    const uint32_t tw = sws::minimizer_windows_per_tile(kBlockThreads, k, w);
+    if (tw == 0) return SWS_ERR_UNSUPPORTED;  // unreachable for k <= 31, w <= 1024
     const uint64_t ntiles = nwin ? (nwin + tw - 1) / tw : 0;
     const uint64_t need = sws::minimizer_workspace_bytes(ntiles);
     if (workspace == nullptr || ws_bytes < need || ((uintptr_t)workspace & 7u)) return SWS_ERR_WORKSPACE;
@@ -234,7 +234,7 @@ int sws_minimizers_workspace(uint64_t n, uint32_t k, uint32_t w, uint64_t* bytes
     if (bytes == nullptr) return SWS_ERR_INVALID;
     const int st = check_minimizer_args(n, k, w, 0);
     if (st != SWS_OK) return st;
-    *bytes = sws::minimizer_workspace_bytes(max_tiles(window_count(n, k, w), w));
+    *bytes = sws::minimizer_workspace_bytes(max_tiles(window_count(n, k, w), k, w));
     return SWS_OK;
 }
 
@@ -278,7 +278,7 @@ int sws_minimizers_noalloc(const uint8_t* seq, uint64_t n, uint32_t k, uint32_t 
     const int st = check_minimizer_call(n, k, w, flags, out_hash, out_pos, capacity, d_count);
     if (st != SWS_OK) return st;
     static_assert(sws::kNoAllocScratchBytes == SWS_NOALLOC_SCRATCH_BYTES, "scratch size");
-    if (sws::minimizer_workspace_bytes(max_tiles(window_count(n, k, w), w)) >
+    if (sws::minimizer_workspace_bytes(max_tiles(window_count(n, k, w), k, w)) >
         sws::kNoAllocScratchBytes)
         return SWS_ERR_WORKSPACE;
     // the scratch address belongs to one device: the stream's must be current
@@ -310,8 +310,8 @@ int check_batch_args(uint64_t total, uint32_t k, uint32_t w, uint32_t flags) {
     return SWS_OK;
 }
 
-uint64_t batch_tiles(uint64_t total, uint32_t w) {
-    const uint32_t tw = sws::batch_tile_windows(w);
+uint64_t batch_tiles(uint64_t total, uint32_t k, uint32_t w) {
+    const uint32_t tw = sws::batch_tile_windows(k, w);
     return total ? (total + tw - 1) / tw : 0;
 }
 
@@ -321,7 +321,7 @@ int sws_minimizers_batch_workspace(uint64_t total_bases, uint32_t nreads, uint32
     if (bytes == nullptr) return SWS_ERR_INVALID;
     const int st = check_batch_args(total_bases, k, w, 0);
     if (st != SWS_OK) return st;
-    *bytes = sws::batch_workspace_bytes(batch_tiles(total_bases, w));
+    *bytes = sws::batch_workspace_bytes(batch_tiles(total_bases, k, w));
     return SWS_OK;
 }
 
@@ -338,7 +338,7 @@ int sws_minimizers_batch_ex(const uint8_t* seqs, const uint64_t* d_offsets, uint
     if (total_bases > 0 && seqs == nullptr) return SWS_ERR_INVALID;
     if (capacity > 0 && (out_hash == nullptr || out_pos == nullptr || out_read == nullptr))
         return SWS_ERR_INVALID;
-    const uint64_t ntiles = batch_tiles(total_bases, w);
+    const uint64_t ntiles = batch_tiles(total_bases, k, w);
     const uint64_t need = sws::batch_workspace_bytes(ntiles);
     if (workspace == nullptr || ws_bytes < need || ((uintptr_t)workspace & 7u)) return SWS_ERR_WORKSPACE;
     if (ntiles == 0) {
@@ -360,7 +360,7 @@ int sws_minimizers_batch_ex(const uint8_t* seqs, const uint64_t* d_offsets, uint
     a.k = k;
     a.w = w;
     a.flags = flags;
-    a.tw = sws::batch_tile_windows(w);
+    a.tw = sws::batch_tile_windows(k, w);
     a.ntiles = ntiles;
     a.out_hash = out_hash;
     a.out_pos = out_pos;

@@ -49,34 +49,64 @@ __device__ __forceinline__ bool base_valid(uint32_t b) {
     return u == 'A' || u == 'C' || u == 'G' || u == 'T';
 }
 
-// Four ASCII bytes at once: per byte, code = bits 1..2 xor-folded, valid iff
-// the upper-cased byte equals "ACGT"[code] (one byte permute builds the
-// expected bytes).  Returns the 4 codes packed first-base-high in 8 bits and
-// sets bit i of *inv4 for an invalid byte i; invalid bytes get code 0.
-__device__ __forceinline__ uint32_t ascii4(uint32_t x, uint32_t* inv4) {
-    const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
-    const uint32_t expect = __builtin_amdgcn_perm(0u, 0x54474341u, c);  // 'T' 'G' 'C' 'A'
-    const uint32_t d = (x & 0xDFDFDFDFu) ^ expect;
-    const uint32_t nz = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;  // byte != 0
-    const uint32_t bad = nz >> 7;                                              // 0 or 1 per byte
-    const uint32_t cv = c & ~(bad * 3u);                                       // invalid -> code 0
-    const uint32_t t = bad | (bad >> 7);
-    *inv4 = (t | (t >> 14)) & 0xFu;
-    return ((cv & 3u) << 6) | ((cv >> 4) & 0x30u) | ((cv >> 14) & 0xCu) | (cv >> 24);
+// Four ASCII bytes at once.  c: per byte, the code (bits 1..2 of the byte,
+// xor-folded) in bits 0..1.  d: per byte, the upper-cased byte xor
+// "ACGT"[code] (one byte permute builds the expected bytes), zero exactly for
+// a base letter.
+__device__ __forceinline__ void ascii4_parts(uint32_t x, uint32_t& c, uint32_t& d) {
+    c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    d = (x & 0xDFDFDFDFu) ^ __builtin_amdgcn_perm(0u, 0x54474341u, c);  // 'T' 'G' 'C' 'A'
+}
+
+// 0x80 in every byte of d that is not zero.
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t d) {
+    return (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;
+}
+
+// The four 2-bit codes of c, byte i's at bits 31 - 2i .. 30 - 2i of the
+// product (first byte highest): the multiplier's terms 2^30, 2^20, 2^10, 2^0
+// move byte i's code (at bit 8i) to bit 30 - 2i, and every other partial
+// product lands in bits 0..21 or past bit 31 without overlapping another, so
+// no carry reaches bits 24..31.
+__device__ __forceinline__ uint32_t codes4_high(uint32_t c) { return c * 0x40100401u; }
+
+// Bit i (i = 0..3) set when byte i of the nonzero_bytes mask z is: after the
+// shift byte i's flag sits at bit 8i, and the multiplier's terms 2^21, 2^14,
+// 2^7, 2^0 move it to bit 21 + i; every other partial product lands in bits
+// 0..16, 29..31 or past bit 31, none overlapping another.
+__device__ __forceinline__ uint32_t invalid4(uint32_t z) {
+    return (((z >> 7) * 0x00204081u) >> 21) & 0xFu;
+}
+
+// 16 bases held as 16 bytes: the code word (first base in bits 31..30) and 16
+// invalid bits (bit i = byte i).  Invalid bytes get code 0.  A lane whose 16
+// bytes are all base letters skips the invalid bookkeeping.
+__device__ __forceinline__ void ascii16_bytes(const uint4& q, uint32_t& code, uint32_t& inv) {
+    uint32_t c0, c1, c2, c3, d0, d1, d2, d3;
+    ascii4_parts(q.x, c0, d0);
+    ascii4_parts(q.y, c1, d1);
+    ascii4_parts(q.z, c2, d2);
+    ascii4_parts(q.w, c3, d3);
+    inv = 0;
+    if ((d0 | d1 | d2 | d3) != 0u) {
+        const uint32_t z0 = nonzero_bytes(d0), z1 = nonzero_bytes(d1);
+        const uint32_t z2 = nonzero_bytes(d2), z3 = nonzero_bytes(d3);
+        inv = invalid4(z0) | (invalid4(z1) << 4) | (invalid4(z2) << 8) | (invalid4(z3) << 12);
+        // 0x03 in each invalid byte: clear its code
+        c0 &= ~((z0 >> 6) | (z0 >> 7));
+        c1 &= ~((z1 >> 6) | (z1 >> 7));
+        c2 &= ~((z2 >> 6) | (z2 >> 7));
+        c3 &= ~((z3 >> 6) | (z3 >> 7));
+    }
+    // bits 31..24 of each product, bytes 0..3 of the code word from the top
+    const uint32_t p0 = codes4_high(c0), p1 = codes4_high(c1);
+    const uint32_t p2 = codes4_high(c2), p3 = codes4_high(c3);
+    code = __builtin_amdgcn_perm(p0, p1, 0x07030C0Cu) | __builtin_amdgcn_perm(p2, p3, 0x0C0C0703u);
 }
 
 // 16 bases starting at `base` (may be negative or run past n): the code word
 // (first base in bits 31..30) and 16 invalid bits (bit i = base + i).  Bases
 // outside [0, n) are invalid with code 0.  Invalid bases get code 0.
-// The code word and invalid bits of 16 bases held as 16 bytes.
-__device__ __forceinline__ void ascii16_bytes(const uint4& q, uint32_t& code, uint32_t& inv) {
-    uint32_t i0, i1, i2, i3;
-    const uint32_t b0 = ascii4(q.x, &i0), b1 = ascii4(q.y, &i1);
-    const uint32_t b2 = ascii4(q.z, &i2), b3 = ascii4(q.w, &i3);
-    code = (b0 << 24) | (b1 << 16) | (b2 << 8) | b3;
-    inv = i0 | (i1 << 4) | (i2 << 8) | (i3 << 12);
-}
-
 __device__ __forceinline__ void ascii16(const uint8_t* __restrict__ seq, int64_t base, uint64_t n,
                                         bool aligned, uint32_t& code, uint32_t& inv) {
     if (aligned && base >= 0 && (uint64_t)base + 16 <= n) {
@@ -140,6 +170,19 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
     return x;
 }
 
+// mix64 of a value below 2^32 (k <= 16), in 32-bit pieces: the first
+// xor-shift is the identity, and the first product is one 32 x 32 -> 64
+// multiply by the constant's low word plus one low multiply by its high word.
+__device__ __forceinline__ uint64_t mix64_u32(uint32_t x) {
+    const uint64_t p = (uint64_t)x * 0x7F4A7C15ull;
+    const uint32_t hi = (uint32_t)(p >> 32) + x * 0x9E3779B9u;
+    uint64_t y = ((uint64_t)hi << 32) | (uint32_t)p;
+    y ^= y >> 29;
+    y *= 0x243F6A8885A308D3ull;
+    y ^= y >> 32;
+    return y;
+}
+
 __device__ __forceinline__ uint32_t revpairs32(uint32_t x) {
     x = __builtin_bitreverse32(x);
     return ((x >> 1) & 0x55555555u) | ((x & 0x55555555u) << 1);
@@ -151,24 +194,28 @@ __device__ __forceinline__ uint64_t revpairs64(uint64_t x) {
 
 // k-mer values (canonical or forward, hashed or not) of the 16 positions of
 // lane t, from the LDS code/invalid words t, t+1, t+2.  bad: bit e set iff the
-// k-mer at position e covers an invalid base.
+// k-mer at position e covers an invalid base.  clean (wave-uniform): no base
+// the wave staged is invalid, so bad is 0 without looking.
 template <bool KM64, int FLAGS = -1>
 __device__ __forceinline__ void lane_kmers(const uint32_t* s_code, const uint32_t* s_inv, int t,
-                                           uint32_t k, bool canon_rt, bool hashed_rt,
+                                           uint32_t k, bool canon_rt, bool hashed_rt, bool clean,
                                            uint64_t (&val)[kR], uint32_t& bad) {
     // FLAGS >= 0 fixes the flags at compile time (bit 0 forward, bit 1 identity)
     const bool canon = FLAGS >= 0 ? (FLAGS & 1) == 0 : canon_rt;
     const bool hashed = FLAGS >= 0 ? (FLAGS & 2) == 0 : hashed_rt;
     const uint32_t w0 = s_code[t], w1 = s_code[t + 1], w2 = s_code[t + 2];
-    const uint64_t M = (uint64_t)s_inv[t] | ((uint64_t)s_inv[t + 1] << 16) |
-                       ((uint64_t)s_inv[t + 2] << 32);
-    uint64_t A = M;
-    uint32_t len = 1;
-    while (2u * len <= k) {
-        A |= A >> len;
-        len *= 2u;
+    bad = 0;
+    if (!clean) {
+        const uint64_t M = (uint64_t)s_inv[t] | ((uint64_t)s_inv[t + 1] << 16) |
+                           ((uint64_t)s_inv[t + 2] << 32);
+        uint64_t A = M;
+        uint32_t len = 1;
+        while (2u * len <= k) {
+            A |= A >> len;
+            len *= 2u;
+        }
+        bad = (uint32_t)((A | (A >> (k - len))) & 0xFFFFu);
     }
-    bad = (uint32_t)((A | (A >> (k - len))) & 0xFFFFu);
 
     const uint64_t hi = ((uint64_t)w0 << 32) | w1;
     const uint64_t mid = ((uint64_t)w1 << 32) | w2;
@@ -203,7 +250,7 @@ __device__ __forceinline__ void lane_kmers(const uint32_t* s_code, const uint32_
                 rc = (rc >> 2) | ((c ^ 3u) << sh);
             }
             const uint32_t cv = (canon && rc < fwd) ? rc : fwd;
-            val[e] = hashed ? mix64((uint64_t)cv) : (uint64_t)cv;
+            val[e] = hashed ? mix64_u32(cv) : (uint64_t)cv;
         }
     }
 }
@@ -222,32 +269,25 @@ __device__ __forceinline__ void stage_bases(const GenomeInput& in, int64_t K0, i
     }
 }
 
-// The 16-base words a wavefront's tile needs, split in two phases so that the
-// global loads of the next tile can be in flight while the current one is
-// computed: `fetch` issues the loads into registers, `commit` converts and
-// stores them into LDS.  Lane l holds word l, and lanes 0 and 1 also words
-// 64 and 65.
+// The 16-base word of a lane in a wavefront tile, split in two phases so
+// that the global load of the next tile can be in flight while the current
+// one is computed: `fetch` issues the load into registers, `commit` converts
+// and stores it into LDS.  Lane l holds the tile's word l.
 struct RawWords {
-    uint4 a, b;  // ASCII: 16 bytes each; 2-bit: .x code word, .y invalid bits
+    uint4 a;  // ASCII: 16 bytes; 2-bit: .x code word, .y invalid bits
 };
 
 template <int IN>
 __device__ __forceinline__ void fetch_words(const GenomeInput& in, int64_t K0, int lane,
                                             RawWords& r) {
     const int64_t b0 = K0 + 16 * (int64_t)lane;
-    const int64_t b1 = K0 + 16 * (int64_t)(kWave + lane);
     if (IN == kInAscii) {
         const bool fast0 = in.aligned && b0 >= 0 && (uint64_t)b0 + 16 <= in.n;
-        const bool fast1 = in.aligned && b1 >= 0 && (uint64_t)b1 + 16 <= in.n;
         r.a = fast0 ? *reinterpret_cast<const uint4*>(in.seq + b0) : make_uint4(0, 0, 0, 0);
-        r.b = (lane < 2 && fast1) ? *reinterpret_cast<const uint4*>(in.seq + b1)
-                                  : make_uint4(0, 0, 0, 0);
     } else {
         uint32_t c, v;
         packed16(in.packed, in.invalid, b0, in.n, c, v);
         r.a = make_uint4(c, v, 0, 0);
-        if (lane < 2) packed16(in.packed, in.invalid, b1, in.n, c, v);
-        r.b = make_uint4(c, v, 0, 0);
     }
 }
 
@@ -260,27 +300,15 @@ __device__ __forceinline__ void ascii_word(const GenomeInput& in, int64_t base, 
     }
 }
 
+// Returns the word's invalid bits.
 template <int IN>
-__device__ __forceinline__ void commit_words(const GenomeInput& in, int64_t K0, int lane,
-                                             const RawWords& r, uint32_t* code, uint32_t* inv) {
-    if (IN == kInAscii) {
-        uint32_t c, v;
-        ascii_word(in, K0 + 16 * (int64_t)lane, r.a, c, v);
-        code[lane] = c;
-        inv[lane] = v;
-        if (lane < 2) {
-            ascii_word(in, K0 + 16 * (int64_t)(kWave + lane), r.b, c, v);
-            code[kWave + lane] = c;
-            inv[kWave + lane] = v;
-        }
-    } else {
-        code[lane] = r.a.x;
-        inv[lane] = r.a.y;
-        if (lane < 2) {
-            code[kWave + lane] = r.b.x;
-            inv[kWave + lane] = r.b.y;
-        }
-    }
+__device__ __forceinline__ uint32_t commit_words(const GenomeInput& in, int64_t K0, int lane,
+                                                 const RawWords& r, uint32_t* code, uint32_t* inv) {
+    uint32_t c = r.a.x, v = r.a.y;
+    if (IN == kInAscii) ascii_word(in, K0 + 16 * (int64_t)lane, r.a, c, v);
+    code[lane] = c;
+    inv[lane] = v;
+    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -549,7 +577,7 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
     {
         uint64_t val[kR];
         uint32_t bad;
-        lane_kmers<KM64>(s_code, s_inv, tid, a.k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u, val,
+        lane_kmers<KM64>(s_code, s_inv, tid, a.k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u, false, val,
                          bad);
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
@@ -688,18 +716,25 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
 // Minimizers, one wavefront per tile (w <= 32).
 //
 // Each wavefront owns a tile of 1024 key positions (16 per lane) and does every
-// step alone: no workgroup barrier after the tile id is known.  The window
-// minimum uses the doubling of Sec. 3.1 for an idempotent operator: with
-// m^(1) = key, m^(2s)_e = min(m^(s)_e, m^(s)_{e+s}), and 2^L the largest power
-// of two not above w, the minimum over [e, e+w) is min(m^(2^L)_e,
+// step alone: no workgroup barrier after the tile id is known.  For w <= 8 the
+// window minimum uses the doubling of Sec. 3.1 for an idempotent operator:
+// with m^(1) = key, m^(2s)_e = min(m^(s)_e, m^(s)_{e+s}), and 2^L the largest
+// power of two not above w, the minimum over [e, e+w) is min(m^(2^L)_e,
 // m^(2^L)_{e+w-2^L}) -- the two halves overlap, which min allows.  The levels
 // run in registers (a lane takes the s values it needs past its run from the
-// next lane); the last, runtime-length shift goes through LDS.  Every min keeps
-// the left operand on ties, so the leftmost position wins.
+// next lane).  For 9 <= w <= 32 block prefix/suffix scans over the lanes' runs
+// take fewer combines (window_min).  Every min keeps the left operand on
+// ties, so the leftmost position wins.
 // ---------------------------------------------------------------------------
+//
+// A wave stages exactly the 1024 bases [K0, K0 + 1024), one 16-base word per
+// lane.  The k-mers at positions past 1024 - k would need bases beyond them:
+// they read the two LDS words after the tile, which are never written, so
+// their keys are unspecified, and the tile owns only windows whose keys all
+// start at or below 1024 - k (wave_tile_windows).
 constexpr int kWaveKeys = kWave * kR;  // 1024 keys per wave tile
 constexpr uint32_t kStage = 512;       // outputs per round of a wave's store compaction
-constexpr int kWaveWords = kWaveKeys / 16 + 2;
+constexpr int kWaveWords = kWaveKeys / 16 + 2;  // the two words past the tile: read, never written
 
 // The value of the next lane (lane 63 reads lane 0) and of the previous lane
 // (lane 0 reads lane 63), by the whole-wave DPP rotates: the move runs in the
@@ -739,25 +774,116 @@ __device__ __forceinline__ void doubling_step(Key (&m)[kR]) {
 }
 
 // The last step shifts by w - 2^L, known only at run time: a uniform switch
-// over the 15 possible values keeps every register index static.
+// over the possible values (w <= 8: at most 3) keeps every register index
+// static.
 template <bool FULL>
 __device__ __forceinline__ void doubling_shift(Key (&m)[kR], uint32_t shift) {
     switch (shift) {
     case 1: doubling_step<1, FULL>(m); break;
     case 2: doubling_step<2, FULL>(m); break;
     case 3: doubling_step<3, FULL>(m); break;
-    case 4: doubling_step<4, FULL>(m); break;
-    case 5: doubling_step<5, FULL>(m); break;
-    case 6: doubling_step<6, FULL>(m); break;
-    case 7: doubling_step<7, FULL>(m); break;
-    case 8: doubling_step<8, FULL>(m); break;
-    case 9: doubling_step<9, FULL>(m); break;
-    case 10: doubling_step<10, FULL>(m); break;
-    case 11: doubling_step<11, FULL>(m); break;
-    case 12: doubling_step<12, FULL>(m); break;
-    case 13: doubling_step<13, FULL>(m); break;
-    case 14: doubling_step<14, FULL>(m); break;
-    case 15: doubling_step<15, FULL>(m); break;
+    default: break;
+    }
+}
+
+// Windows of 9 to 32 keys: the block prefix/suffix scheme of Sec. 2.2, with
+// each lane's run of 16 keys as a block.  A window that leaves the run is a
+// suffix of the run combined with a prefix of the next run (w <= 17), or with
+// the whole next run and a prefix of the one after (w > 17); a window inside
+// the run (w <= 16) crosses its middle, so it is a suffix of the first half
+// combined with a prefix of the second.  Per position this takes about 3
+// combines where the doubling takes ceil(log2 w) (4 at w = 10, 5 at w = 19).
+// Every combine keeps the earlier keys on the left, so ties still go to the
+// leftmost position.
+//
+// Order of work, to keep few keys live: the prefixes first (the previous lane
+// takes them as they form), then the suffixes from the end of the run, each
+// output written in place as soon as its suffix exists.
+template <int W, bool FULL>
+__device__ __forceinline__ void window_min_runs(Key (&m)[kR]) {
+    static_assert(W >= 9 && W <= 32, "windows of 9 to 32 keys");
+    if (W <= 16) {
+        Key pn[W - 1];  // the next run's prefixes: keys 0 .. j, j <= W - 2
+        Key pb[8];      // this run's keys 8 .. 8 + i
+        Key p = m[0];
+        pn[0] = from_next_lane(p);
+#pragma unroll
+        for (int j = 1; j < 8; ++j) {
+            p = key_min<FULL>(p, m[j]);
+            if (j <= W - 2) pn[j] = from_next_lane(p);
+        }
+        pb[0] = m[8];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) pb[i] = key_min<FULL>(pb[i - 1], m[8 + i]);
+#pragma unroll
+        for (int j = 8; j <= W - 2; ++j) pn[j] = from_next_lane(key_min<FULL>(p, pb[j - 8]));
+        // windows e >= 17 - W leave the run: keys e .. 15, then the next
+        // run's keys 0 .. e + W - 17
+        Key sb = m[15];
+        m[15] = key_min<FULL>(sb, pn[W - 2]);
+#pragma unroll
+        for (int e = 14; e >= 8; --e) {
+            sb = key_min<FULL>(m[e], sb);
+            m[e] = key_min<FULL>(sb, pn[e + W - 17]);
+        }
+        // sb: keys 8 .. 15.  Windows e <= 16 - W (e <= 7) stay in the run:
+        // keys e .. 7, then keys 8 .. e + W - 1.
+        Key sa = m[7];
+#pragma unroll
+        for (int e = 7; e >= 0; --e) {
+            if (e < 7) sa = key_min<FULL>(m[e], sa);
+            if (e >= 17 - W) m[e] = key_min<FULL>(key_min<FULL>(sa, sb), pn[e + W - 17]);
+            else m[e] = key_min<FULL>(sa, pb[e + W - 9]);
+        }
+    } else {
+        constexpr int NN = W > 17 ? W - 17 : 1;
+        Key pn[kR];   // the next run's prefixes: keys 0 .. j
+        Key pnn[NN];  // the prefixes of the run after next, j <= W - 18
+        Key p = m[0];
+        pn[0] = from_next_lane(p);
+#pragma unroll
+        for (int j = 1; j < kR; ++j) {
+            p = key_min<FULL>(p, m[j]);
+            pn[j] = from_next_lane(p);
+        }
+#pragma unroll
+        for (int j = 0; j < W - 17; ++j) pnn[j] = from_next_lane(pn[j]);
+        // window e: keys e .. 15, the next run's keys 0 .. e + W - 17 (all
+        // 16 of them when e + W - 17 > 15, then the run after next's keys
+        // 0 .. e + W - 33)
+        Key sfx = m[kR - 1];
+#pragma unroll
+        for (int e = kR - 1; e >= 0; --e) {
+            if (e < kR - 1) sfx = key_min<FULL>(m[e], sfx);
+            if (e <= 32 - W) m[e] = key_min<FULL>(sfx, pn[e + W - 17]);
+            else m[e] = key_min<FULL>(key_min<FULL>(sfx, pn[kR - 1]), pnn[e + W - 33]);
+        }
+    }
+}
+
+// The minimum of every window of w keys (1 <= w <= 32) starting in the run,
+// in place: doubling for w <= 8, runs for larger w (a uniform switch keeps
+// every register index static).
+template <bool FULL>
+__device__ __forceinline__ void window_min(Key (&m)[kR], uint32_t w) {
+    if (w <= 8u) {
+        uint32_t L = 1;
+        if (2u <= w) { doubling_step<1, FULL>(m); L = 2; }
+        if (4u <= w) { doubling_step<2, FULL>(m); L = 4; }
+        if (8u <= w) { doubling_step<4, FULL>(m); L = 8; }
+        doubling_shift<FULL>(m, w - L);  // 0 <= w - L < L <= 8
+        return;
+    }
+    switch (w) {
+#define SWS_RUNS_CASE(W) \
+    case W: window_min_runs<W, FULL>(m); break;
+    SWS_RUNS_CASE(9) SWS_RUNS_CASE(10) SWS_RUNS_CASE(11) SWS_RUNS_CASE(12)
+    SWS_RUNS_CASE(13) SWS_RUNS_CASE(14) SWS_RUNS_CASE(15) SWS_RUNS_CASE(16)
+    SWS_RUNS_CASE(17) SWS_RUNS_CASE(18) SWS_RUNS_CASE(19) SWS_RUNS_CASE(20)
+    SWS_RUNS_CASE(21) SWS_RUNS_CASE(22) SWS_RUNS_CASE(23) SWS_RUNS_CASE(24)
+    SWS_RUNS_CASE(25) SWS_RUNS_CASE(26) SWS_RUNS_CASE(27) SWS_RUNS_CASE(28)
+    SWS_RUNS_CASE(29) SWS_RUNS_CASE(30) SWS_RUNS_CASE(31) SWS_RUNS_CASE(32)
+#undef SWS_RUNS_CASE
     default: break;
     }
 }
@@ -810,13 +936,39 @@ __device__ __forceinline__ uint32_t previous_window_bits(uint32_t wbad) {
     return ((wbad << 1) | ((from_prev_lane(wbad) >> 15) & 1u)) & 0xFFFFu;
 }
 
-// From the 2-bit layout the kernel runs 5 waves per SIMD (96 VGPRs, a few
-// spilled: 0.1540 against 0.1571 ms at 64 Mbases); from ASCII, where the
-// decode needs more registers, that measured slower (0.1787 against 0.1720),
-// so it keeps the compiler's choice (101 VGPRs, 4 waves).
+// The keys of a lane's 16 positions: value and tag = tile position.  With
+// any_bad (wave-uniform) the k-mers flagged in bad become invalid keys:
+// all-ones without FULL (no valid k-mer reaches it, so one never wins), the
+// invalid tag bit with FULL.
+template <bool FULL>
+__device__ __forceinline__ void make_keys(const uint64_t (&val)[kR], uint32_t bad, bool any_bad,
+                                          uint32_t tbase, Key (&m)[kR]) {
+#pragma unroll
+    for (int e = 0; e < kR; ++e) {
+        m[e].lo = (uint32_t)val[e];
+        m[e].hi = (uint32_t)(val[e] >> 32);
+        m[e].tag = tbase + e;
+    }
+    if (!any_bad) return;
+#pragma unroll
+    for (int e = 0; e < kR; ++e) {
+        if (FULL) {
+            const bool iv = (bad >> e) & 1u;
+            m[e].lo = iv ? 0xFFFFFFFFu : m[e].lo;
+            m[e].hi = iv ? 0xFFFFFFFFu : m[e].hi;
+            m[e].tag |= iv ? kInvalidTag : 0u;
+        } else {
+            const uint32_t ivm = 0u - ((bad >> e) & 1u);
+            m[e].lo |= ivm;
+            m[e].hi |= ivm;
+        }
+    }
+}
+
+// Both input layouts run 4 waves per SIMD (at most 128 VGPRs; the window
+// minimum of w > 8 holds up to 32 keys at once).
 template <int NT, int IN, bool KM64, bool FULL, int FLAGS>
-__global__ __launch_bounds__(NT, IN == kIn2bit ? 5 : 1) void minimizer_wave_kernel(GenomeInput in,
-                                                                                   MinimizerArgs a) {
+__global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, MinimizerArgs a) {
     constexpr int NWV = NT / kWave;
     static_assert(NWV <= kWave, "one lane per wave of the workgroup");
     __shared__ uint32_t s_code[NWV][kWaveWords], s_inv[NWV][kWaveWords];
@@ -848,8 +1000,12 @@ __global__ __launch_bounds__(NT, IN == kIn2bit ? 5 : 1) void minimizer_wave_kern
         RawWords raw;
         fetch_words<IN>(in, K0, lane, raw);
         // 1. bases
-        commit_words<IN>(in, K0, lane, raw, code, inv);
+        const uint32_t inv_word = commit_words<IN>(in, K0, lane, raw, code, inv);
         wave_lds_sync();
+        // a wave whose 1024 bases are all valid skips every invalid-bit step
+        // (the keys past 1024 - k, whose k-mers run into the unwritten words,
+        // belong to no window the tile stores)
+        const bool clean = __ballot(inv_word != 0u) == 0ull;
 
         // 2. keys.  Without FULL an invalid k-mer gets the all-ones key, which
         //    no valid k-mer reaches, so it never wins against one; whether a
@@ -860,39 +1016,18 @@ __global__ __launch_bounds__(NT, IN == kIn2bit ? 5 : 1) void minimizer_wave_kern
             uint64_t val[kR];
             uint32_t bad;
             lane_kmers<KM64, FLAGS>(code, inv, lane, a.k, (a.flags & 1u) == 0u,
-                                    (a.flags & 2u) == 0u, val, bad);
+                                    (a.flags & 2u) == 0u, clean, val, bad);
             const bool split = FLAGS != 0 && (a.flags & kSplitFlag);
-            if (!FULL || split) {
+            if ((!FULL || split) && !clean) {
                 const uint64_t ext = run_bits3(bad);
                 if (!FULL) wnone = window_all_invalid(ext, w);
                 if (split) wbad = window_holds_invalid(ext, w);
             }
-            const uint32_t tbase = (uint32_t)lane * kR;
-#pragma unroll
-            for (int e = 0; e < kR; ++e) {
-                if (FULL) {
-                    const bool iv = (bad >> e) & 1u;
-                    m[e].lo = iv ? 0xFFFFFFFFu : (uint32_t)val[e];
-                    m[e].hi = iv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
-                    m[e].tag = (tbase + e) | (iv ? kInvalidTag : 0u);
-                } else {
-                    const uint32_t ivm = 0u - ((bad >> e) & 1u);
-                    m[e].lo = (uint32_t)val[e] | ivm;
-                    m[e].hi = (uint32_t)(val[e] >> 32) | ivm;
-                    m[e].tag = tbase + e;
-                }
-            }
+            make_keys<FULL>(val, bad, !clean, (uint32_t)lane * kR, m);
         }
 
-        // 3. window minimum by doubling: levels 1, 2, 4, 8, 16 while 2s <= w,
-        //    then one step by w - 2^L
-        uint32_t L = 1;
-        if (2u <= w) { doubling_step<1, FULL>(m); L = 2; }
-        if (4u <= w) { doubling_step<2, FULL>(m); L = 4; }
-        if (8u <= w) { doubling_step<4, FULL>(m); L = 8; }
-        if (16u <= w) { doubling_step<8, FULL>(m); L = 16; }
-        if (32u <= w) { doubling_step<16, FULL>(m); L = 32; }
-        doubling_shift<FULL>(m, w - L);  // 0 <= w - L < L <= 32
+        // 3. window minimum
+        window_min<FULL>(m, w);
 
         // 4. dedup, as bit masks over the lane's 16 windows: window j is
         //    stored iff owned, valid and its minimum sits at another position
@@ -1125,13 +1260,14 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
         const uint32_t wcross = or_after(B, k + w - 2u);  // window e spans a read start
 
         // bases and keys
-        commit_words<kInAscii>(in, K0, lane, raw, code, inv);
+        const uint32_t inv_word = commit_words<kInAscii>(in, K0, lane, raw, code, inv);
         wave_lds_sync();
+        const bool clean = __ballot(inv_word != 0u) == 0ull;  // as in minimizer_wave_kernel
         {
             uint64_t val[kR];
             uint32_t bad;
             lane_kmers<KM64, FLAGS>(code, inv, lane, k, (a.flags & 1u) == 0u, (a.flags & 2u) == 0u,
-                                    val, bad);
+                                    clean, val, bad);
             bad |= kcross;
             const bool split = FLAGS != 0 && (a.flags & kSplitFlag);
             if (!FULL || split) {
@@ -1139,29 +1275,9 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
                 if (!FULL) wnone = window_all_invalid(ext, w);
                 if (split) wbad = window_holds_invalid(ext, w);
             }
-            const uint32_t tbase = (uint32_t)lane * kR;
-#pragma unroll
-            for (int e = 0; e < kR; ++e) {
-                if (FULL) {
-                    const bool iv = (bad >> e) & 1u;
-                    m[e].lo = iv ? 0xFFFFFFFFu : (uint32_t)val[e];
-                    m[e].hi = iv ? 0xFFFFFFFFu : (uint32_t)(val[e] >> 32);
-                    m[e].tag = (tbase + e) | (iv ? kInvalidTag : 0u);
-                } else {
-                    const uint32_t ivm = 0u - ((bad >> e) & 1u);
-                    m[e].lo = (uint32_t)val[e] | ivm;
-                    m[e].hi = (uint32_t)(val[e] >> 32) | ivm;
-                    m[e].tag = tbase + e;
-                }
-            }
+            make_keys<FULL>(val, bad, true, (uint32_t)lane * kR, m);
         }
-        uint32_t L = 1;
-        if (2u <= w) { doubling_step<1, FULL>(m); L = 2; }
-        if (4u <= w) { doubling_step<2, FULL>(m); L = 4; }
-        if (8u <= w) { doubling_step<4, FULL>(m); L = 8; }
-        if (16u <= w) { doubling_step<8, FULL>(m); L = 16; }
-        if (32u <= w) { doubling_step<16, FULL>(m); L = 32; }
-        doubling_shift<FULL>(m, w - L);
+        window_min<FULL>(m, w);
 
         // dedup, restarting at read starts (bit masks as in the single-sequence
         // kernel)
@@ -1400,7 +1516,16 @@ uint64_t batch_workspace_bytes(uint64_t ntiles) {
     return kWsStatusOffset + (8ull * kStatusStride + 4ull) * ntiles;
 }
 
-uint32_t batch_tile_windows(uint32_t w) { return minimizer_tile_windows(kWave, w); }
+// Windows a wave tile stores: its 1024 keys less the 16 before its first
+// window, the w - 1 keys the last window reaches past its start and the
+// k - 1 keys whose k-mers run past the tile's bases; a multiple of 16.
+uint32_t wave_tile_windows(uint32_t k, uint32_t w) {
+    const uint32_t need = 16u + (w - 1u) + (k - 1u);
+    if ((uint32_t)kWaveKeys < need + 16u) return 0;
+    return ((uint32_t)kWaveKeys - need) & ~15u;
+}
+
+uint32_t batch_tile_windows(uint32_t k, uint32_t w) { return wave_tile_windows(k, w); }
 
 uint32_t minimizer_tile_windows(uint32_t nt, uint32_t w) {
     const uint32_t P = nt * kR;
@@ -1412,8 +1537,8 @@ uint32_t minimizer_wave_max_window() { return 32; }
 
 // Windows stored per tile: one wavefront's 1024 keys when w <= 32, else the
 // workgroup's 16 * nt keys.
-uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t w) {
-    return w <= minimizer_wave_max_window() ? minimizer_tile_windows(kWave, w)
+uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t k, uint32_t w) {
+    return w <= minimizer_wave_max_window() ? wave_tile_windows(k, w)
                                             : minimizer_tile_windows(nt, w);
 }
 

@@ -80,13 +80,13 @@ int launch_zero(uint64_t* p, uint64_t words, hipStream_t s);
 int launch_minimizers_batch(const GenomeInput& in, BatchArgs a, uint32_t nt, void* workspace,
                             hipStream_t s);
 uint64_t batch_workspace_bytes(uint64_t ntiles);
-uint32_t batch_tile_windows(uint32_t w);
+uint32_t batch_tile_windows(uint32_t k, uint32_t w);
 int launch_pack2bit(const uint8_t* seq, uint64_t n, uint32_t* packed, uint32_t* invalid,
                     hipStream_t s);
 int launch_kmers(const GenomeInput& in, uint32_t k, uint32_t flags, uint64_t* out, hipStream_t s);
 uint32_t minimizer_tile_windows(uint32_t nt, uint32_t w);
 uint32_t minimizer_wave_max_window();  // largest w of the wave-tile kernels
-uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t w);
+uint32_t minimizer_windows_per_tile(uint32_t nt, uint32_t k, uint32_t w);
 uint64_t minimizer_workspace_bytes(uint64_t ntiles);
 // The allocation-free minimizer call's scratch: a static device array of this
 // many bytes.  noalloc_scratch(device) is its address on `device`, which must

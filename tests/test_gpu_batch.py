@@ -45,6 +45,22 @@ def test_random_batches(k, w):
             check_batch(torch, seqs, off, k, w, can, hsh, tag="flags")
 
 
+@pytest.mark.parametrize("w", list(range(1, 33)))
+def test_every_window_up_to_32(w):
+    """Every window length of the batched kernel, with k cycled so that short,
+    long and FULL keys all meet the run pairings (k + w <= 49); reads with N
+    and reads without."""
+    torch = torch_cuda()
+    ks = (15, 1, 31, 16, 17, 7, 22, 30, 11)
+    k = min(ks[w % len(ks)], 49 - w)
+    rng = np.random.default_rng(500 + w)
+    lens = rng.integers(0, 600, 120)
+    seqs, off = make_batch(lens, seed=w, n_rate=0.01)
+    check_batch(torch, seqs, off, k, w, tag="every w, N")
+    seqs, off = make_batch(rng.integers(200, 3000, 12), seed=w + 1, n_rate=0.0, lower=0.0)
+    check_batch(torch, seqs, off, k, w, tag="every w, valid")
+
+
 def test_edges():
     torch = torch_cuda()
     k, w = 15, 10

@@ -122,6 +122,37 @@ def test_minimizers_random(k, w):
             assert_same_minimizers(torch, s, k, w, can, hsh, tag="flags")
 
 
+# k values cycled over w so that every window length meets short, long (> 16)
+# and FULL (hashed k >= 30) keys
+_EVERY_K = (15, 1, 31, 16, 17, 7, 22, 30, 11)
+
+
+@pytest.mark.parametrize("w", list(range(1, 33)))
+def test_every_window_up_to_32(w):
+    """Every window length of the wave-tile kernel (each has its own pairing
+    of run prefixes and suffixes, or doubling steps): sequences over several
+    wave tiles with a ragged end, all valid (waves skip the invalid bits), with
+    scattered N, and with one N run between valid stretches (valid and invalid
+    waves in one launch); ASCII and 2-bit input."""
+    torch = torch_cuda()
+    import paper_1811_10074_amd as sws
+    k = _EVERY_K[w % len(_EVERY_K)]
+    n = 5 * 1024 + 517
+    for variant in range(3):
+        s = inputs.dna(n, seed=1000 + 3 * w + variant, n_rate=0.01 if variant == 1 else 0.0)
+        if variant == 2:
+            s[2100:2100 + 37] = ord("N")
+        assert_same_minimizers(torch, s, k, w, tag="every w, variant %d" % variant)
+        sd = seq_dev(torch, s)
+        packed, inv = sws.pack2bit(sd)
+        h, p = sws.minimizers_2bit(packed, inv if variant else None, n, k, w)
+        torch.cuda.synchronize()
+        eh, ep = oracle.minimizers(s, k, w)
+        assert np.array_equal(host_u32(p), ep) and np.array_equal(host_u64(h), eh), (k, w, variant)
+    s = inputs.dna(3 * 1024 + 100, seed=w, n_rate=0.005)
+    assert_same_minimizers(torch, s, k, w, canonical=False, hashed=False, tag="forward identity")
+
+
 @pytest.mark.parametrize("w", [33, 64, 500, 992, 993, 1000, 1024])
 def test_block_kernel_workspace_sizes(w):
     """Windows above 32 run on the 256-thread block kernel: the workspace the
