@@ -218,37 +218,41 @@ __device__ __forceinline__ void lane_kmers(const uint32_t* s_code, const uint32_
     }
 
     const uint64_t hi = ((uint64_t)w0 << 32) | w1;
-    const uint64_t mid = ((uint64_t)w1 << 32) | w2;
-    // incoming bases k .. k+15 (base k-1+e enters at position e)
-    const uint32_t inW = k < 16u ? (uint32_t)((hi << (2u * k)) >> 32)
-                                 : (uint32_t)((mid << (2u * k - 32u)) >> 32);
     if (KM64) {
-        const uint64_t mask = (1ull << (2u * k)) - 1ull;
-        uint64_t fwd = hi >> (64u - 2u * k);
-        uint64_t rc = revpairs64(~fwd) >> (64u - 2u * k);
-        const uint32_t sh = 2u * k - 2u;
+        // The 48 bases of words t .. t + 2 hold every k-mer of the run (bases
+        // e .. e + k - 1 <= 45).  The 64 bits from base e on, shifted right by
+        // 64 - 2k, are k-mer e's forward value; in R2:R1:R0, the reverse
+        // complement of all 48 bases (base i complemented at bits 2i + 1 ..
+        // 2i), its reverse complement is the 2k bits from bit 2e.  Funnel
+        // shifts by constants, no recurrence between positions.
+        const uint32_t R0 = revpairs32(~w0), R1 = revpairs32(~w1), R2 = revpairs32(~w2);
+        const uint32_t mhi = (1u << (2u * k - 32u)) - 1u;  // k >= 17
+        const uint32_t fsh = 64u - 2u * k;
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
-            if (e > 0) {
-                const uint32_t c = (inW >> (30 - 2 * (e - 1))) & 3u;
-                fwd = ((fwd << 2) | c) & mask;
-                rc = (rc >> 2) | ((uint64_t)(c ^ 3u) << sh);
-            }
+            const uint32_t uh = e == 0 ? w0 : __builtin_amdgcn_alignbit(w0, w1, 32 - 2 * e);
+            const uint32_t ul = e == 0 ? w1 : __builtin_amdgcn_alignbit(w1, w2, 32 - 2 * e);
+            const uint64_t fwd = (((uint64_t)uh << 32) | ul) >> fsh;
+            const uint32_t rl = e == 0 ? R0 : __builtin_amdgcn_alignbit(R1, R0, 2 * e);
+            const uint32_t rh = (e == 0 ? R1 : __builtin_amdgcn_alignbit(R2, R1, 2 * e)) & mhi;
+            const uint64_t rc = ((uint64_t)rh << 32) | rl;
             const uint64_t cv = (canon && rc < fwd) ? rc : fwd;
             val[e] = hashed ? mix64(cv) : cv;
         }
     } else {
+        // The 32 bases of words t, t + 1 hold every k-mer of the run (bases
+        // e .. e + k - 1 <= 30).  In G = hi >> (34 - 2k) k-mer e's forward
+        // value is the 2k bits from bit 30 - 2e; in R, the reverse complement
+        // of all 32 bases (base i complemented at bits 2i + 1 .. 2i), k-mer
+        // e's reverse complement is the 2k bits from bit 2e.  Each is one
+        // funnel shift and a mask, with no recurrence between positions.
         const uint32_t mask = k == 16u ? 0xFFFFFFFFu : ((1u << (2u * k)) - 1u);
-        uint32_t fwd = (uint32_t)(hi >> (64u - 2u * k));
-        uint32_t rc = revpairs32(~fwd) >> (32u - 2u * k);
-        const uint32_t sh = 2u * k - 2u;
+        const uint64_t G = hi >> (34u - 2u * k);
+        const uint64_t R = revpairs64(~hi);
 #pragma unroll
         for (int e = 0; e < kR; ++e) {
-            if (e > 0) {
-                const uint32_t c = (inW >> (30 - 2 * (e - 1))) & 3u;
-                fwd = ((fwd << 2) | c) & mask;
-                rc = (rc >> 2) | ((c ^ 3u) << sh);
-            }
+            const uint32_t fwd = (uint32_t)(G >> (30 - 2 * e)) & mask;
+            const uint32_t rc = (uint32_t)(R >> (2 * e)) & mask;
             const uint32_t cv = (canon && rc < fwd) ? rc : fwd;
             val[e] = hashed ? mix64_u32(cv) : (uint64_t)cv;
         }
@@ -669,12 +673,7 @@ __global__ __launch_bounds__(NT) void minimizer_kernel(GenomeInput in, Minimizer
 
     // 5. ordered compaction
     const uint32_t cnt = (uint32_t)__builtin_popcount(emit);
-    uint32_t incl = cnt;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t o = shfl(incl, lane, -d);
-        if (lane >= d) incl += o;
-    }
+    uint32_t incl = wave_inclusive_sum(cnt);
     if (lane == kWave - 1) s_wsum[wv] = incl;
     __syncthreads();  // also: every read of s_h / s_tag above is complete
     uint32_t wbase = 0, total = 0;
@@ -888,6 +887,17 @@ __device__ __forceinline__ void window_min(Key (&m)[kR], uint32_t w) {
     }
 }
 
+// Bit e set when window e's minimum sits at another position than window
+// e - 1's (window -1: the previous lane's last).  Built from the last window
+// down: each step doubles the bits so far and adds the next comparison, so
+// window e ends at bit e.
+__device__ __forceinline__ uint32_t changed_bits(const Key (&m)[kR]) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int e = kR - 1; e > 0; --e) r = r + r + (m[e].tag != m[e - 1].tag ? 1u : 0u);
+    return r + r + (m[0].tag != from_prev_lane(m[kR - 1].tag) ? 1u : 0u);
+}
+
 // OR over the `len` bits following each of bits 0..15: bit e of the result is
 // set iff some bit in [e+1, e+len] of x is.  len <= 62 - 15.
 __device__ __forceinline__ uint32_t or_after(uint64_t x, uint32_t len) {
@@ -1034,13 +1044,7 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
         //    than the previous window's (the first window of the sequence has
         //    no previous one)
         {
-            uint32_t prev = from_prev_lane(m[kR - 1].tag);
-            uint32_t fresh = 0;
-#pragma unroll
-            for (int e = 0; e < kR; ++e) {
-                fresh |= (m[e].tag != prev ? 1u : 0u) << e;
-                prev = m[e].tag;
-            }
+            uint32_t fresh = changed_bits(m);
             if (p0 == 0 && lane == 1) fresh |= 1u;  // window 0 is j = 16
             if (FLAGS != 0 && (a.flags & kSplitFlag))
                 fresh |= previous_window_bits(wbad);
@@ -1059,12 +1063,7 @@ __global__ __launch_bounds__(NT) void minimizer_wave_kernel(GenomeInput in, Mini
     // 5. ordered compaction: lane prefix, workgroup sum, look-back, stores
     //    from registers
     const uint32_t cnt = (uint32_t)__builtin_popcount(emit);
-    uint32_t incl = cnt;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t o = shfl(incl, lane, -d);
-        if (lane >= d) incl += o;
-    }
+    uint32_t incl = wave_inclusive_sum(cnt);
     if (lane == kWave - 1) s_cnt[wv] = incl;
     __syncthreads();
     if (wv == 0) {
@@ -1183,11 +1182,12 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     __shared__ uint32_t s_rid[NWV][kReadSlots];
     __shared__ uint32_t s_rstart[NWV][kReadSlots];
     __shared__ uint32_t s_lexcl[NWV][kWave], s_lemit[NWV][kWave];
+    // per lane run: listed read starts before it, and its 16 read-start bits
+    __shared__ uint32_t s_lstart[NWV][kWave], s_lbits[NWV][kWave];
     __shared__ uint32_t s_cnt[NWV];  // stores per wave tile
     __shared__ uint64_t s_base;      // stores before the workgroup
     __shared__ uint64_t s_stage_hash[NWV][kBatchStage];
     __shared__ uint32_t s_stage_pos[NWV][kBatchStage];
-    __shared__ uint32_t s_stage_read[NWV][kBatchStage];
 
     const int lane = lane_id();
     const int wv = wave_id();
@@ -1282,13 +1282,7 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
         // dedup, restarting at read starts (bit masks as in the single-sequence
         // kernel)
         {
-            uint32_t prev = from_prev_lane(m[kR - 1].tag);
-            uint32_t fresh = (uint32_t)B & 0xFFFFu;
-#pragma unroll
-            for (int e = 0; e < kR; ++e) {
-                fresh |= (m[e].tag != prev ? 1u : 0u) << e;
-                prev = m[e].tag;
-            }
+            uint32_t fresh = changed_bits(m) | ((uint32_t)B & 0xFFFFu);
             if (FLAGS != 0 && (a.flags & kSplitFlag))
                 fresh |= previous_window_bits(wbad);
             uint32_t valid = ~(wnone | wbad | wcross);
@@ -1303,19 +1297,12 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
         }
         cnt = (uint32_t)__builtin_popcount(emit);
         starts = (uint32_t)__builtin_popcountll(B & 0xFFFFull);
-        incl = cnt;
-        sincl = starts;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t o = shfl(incl, lane, -d);
-            const uint32_t so = shfl(sincl, lane, -d);
-            if (lane >= d) {
-                incl += o;
-                sincl += so;
-            }
-        }
+        incl = wave_inclusive_sum(cnt);
+        sincl = wave_inclusive_sum(starts);
         s_lexcl[wv][lane] = incl - cnt;
         s_lemit[wv][lane] = emit;
+        s_lstart[wv][lane] = pre + sincl - starts;
+        s_lbits[wv][lane] = (uint32_t)B & 0xFFFFu;
     }
 
     const uint32_t total = lane_value(incl, kWave - 1);
@@ -1336,8 +1323,6 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     if (!has_tile) return;  // no barrier follows
     uint64_t excl = s_base;
     for (int v = 0; v < wv; ++v) excl += s_cnt[v];
-    // read rank of position e: listed reads starting at or before it, minus one
-    const int32_t rank0 = (int32_t)(pre + sincl - starts) - 1;
     // Compaction through wave-private LDS, as in minimizer_wave_kernel: lane
     // l writes its outputs at their ranks within the wave, then consecutive
     // lanes store consecutive outputs.  More than kBatchStage outputs take
@@ -1347,28 +1332,43 @@ __global__ __launch_bounds__(NT) void minimizer_batch_kernel(GenomeInput in, Bat
     if (excl + total_w > a.capacity) lim = excl >= a.capacity ? 0u : (uint32_t)(a.capacity - excl);
     uint64_t* sh = s_stage_hash[wv];
     uint32_t* sp = s_stage_pos[wv];
-    uint32_t* sr = s_stage_read[wv];
     for (uint32_t c = 0; c < lim; c += kBatchStage) {
-        // stage each output's hash, absolute position and read rank (the
-        // lanes' runs stay in registers: only unrolled loops touch them)
+        // stage each output's hash and tile position (the lanes' runs stay
+        // in registers: only unrolled loops touch them)
         uint32_t j = incl - cnt - c;  // rank - c, mod 2^32
+        if (total_w <= kBatchStage) {  // one round, the usual case: every rank fits
 #pragma unroll
-        for (int e = 0; e < kR; ++e) {
-            if ((emit >> e) & 1u) {
-                if (j < kBatchStage) {
+            for (int e = 0; e < kR; ++e) {
+                if ((emit >> e) & 1u) {
                     sh[j] = ((uint64_t)m[e].hi << 32) | m[e].lo;
-                    sp[j] = (uint32_t)(K0 + (int64_t)(m[e].tag & (FULL ? 0x7FFFu : 0xFFFFu)));
-                    sr[j] = (uint32_t)(rank0 + __builtin_popcountll(B & ((2ull << e) - 1ull)));
+                    sp[j] = m[e].tag & (FULL ? 0x7FFFu : 0xFFFFu);
+                    ++j;
                 }
-                ++j;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < kR; ++e) {
+                if ((emit >> e) & 1u) {
+                    if (j < kBatchStage) {
+                        sh[j] = ((uint64_t)m[e].hi << 32) | m[e].lo;
+                        sp[j] = m[e].tag & (FULL ? 0x7FFFu : 0xFFFFu);
+                    }
+                    ++j;
+                }
             }
         }
         wave_lds_sync();
-        // resolve ranks to reads and store, consecutive lanes on consecutive
-        // outputs
+        // resolve positions to reads and store, consecutive lanes on
+        // consecutive outputs.  The read of tile position t is the listed
+        // read of rank (starts before t's lane run) + (starts in the run up
+        // to t) - 1.
         const uint32_t nc = min(kBatchStage, lim - c);
         for (uint32_t q = (uint32_t)lane; q < nc; q += kWave) {
-            const uint32_t pos = sp[q], rk = sr[q];
+            const uint32_t t = sp[q];
+            const uint32_t l = t >> 4, e = t & 15u;
+            const uint32_t rk = s_lstart[wv][l] +
+                                (uint32_t)__builtin_popcount(s_lbits[wv][l] & ((2u << e) - 1u)) - 1u;
+            const uint32_t pos = (uint32_t)(K0 + (int64_t)t);
             uint32_t rr, rs;
             if (rk < kReadSlots && rk < nlisted) {
                 rr = rid[rk];

@@ -149,12 +149,7 @@ __global__ __launch_bounds__(kSeedNT) void seed_scan_kernel(uint32_t* __restrict
     for (uint64_t base = 0; base < ntiles; base += kSeedNT) {
         const uint64_t i = base + threadIdx.x;
         const uint32_t v = i < ntiles ? row[i] : 0u;
-        uint32_t incl = v;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t o = shfl(incl, lane, -d);
-            if (lane >= d) incl += o;
-        }
+        uint32_t incl = wave_inclusive_sum(v);
         if (lane == kWave - 1) part[wv] = incl;
         __syncthreads();
         uint32_t before = carry;
@@ -174,12 +169,7 @@ __device__ __forceinline__ uint32_t wave_scan256(uint32_t* a, int lane) {
     uint32_t run = 0;
     for (int c = 0; c < kDigits; c += kWave) {
         const uint32_t v = a[c + lane];
-        uint32_t incl = v;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t o = shfl(incl, lane, -d);
-            if (lane >= d) incl += o;
-        }
+        uint32_t incl = wave_inclusive_sum(v);
         a[c + lane] = run + incl - v;
         run += lane_value(incl, kWave - 1);
     }

@@ -52,6 +52,21 @@ __device__ __forceinline__ uint2 shfl(uint2 v, int lane, int delta) {
     return make_uint2(shfl(v.x, lane, delta), shfl(v.y, lane, delta));
 }
 
+// Inclusive prefix sum over the wave's 64 lanes by DPP: four row shifts sum
+// within each row of 16 lanes, then two row broadcasts carry row totals
+// forward (lane 15 into row 1, lane 47 into row 3, then lane 31 into rows 2
+// and 3).  Each step is one VALU add with a DPP source.  Every lane of the
+// wave must be active.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
+}
+
 // A minimizer key: 64-bit value (hash or k-mer) split in two words, and a tag
 // holding the position inside the tile (bits 0..14) and an invalid flag
 // (bit 15).
