@@ -219,19 +219,22 @@ def few_waves():
     sws.set_sliding_waves(0)
 
 
-@pytest.mark.parametrize("waves", [1, 2, 3])
+@pytest.mark.parametrize("waves", [1, 2, 3, 5])
 @pytest.mark.parametrize("op", ["add", "min", "max", "affine"])
 def test_long_streams_per_wave(few_waves, waves, op):
     """Few wavefronts, each streaming many slabs: the unchecked steady-state
-    loop, its peeled first step, the last in-range step of a wave and the
-    checked steps at the end, with n on either side of the slab boundaries
-    that decide between them."""
+    loop, its peeled first step, the step that prefetches the next wave's
+    first slab, the last in-range steps of a wave and the checked steps at
+    the end, with n on either side of the slab boundaries that decide between
+    them; waves of one slab, of fewer slabs than are in flight, and of odd and
+    even slab counts (two register buffers alternate)."""
     torch = torch_cuda()
     few_waves(waves)
     seed = {"add": 21, "min": 22, "max": 23, "affine": 24}[op]
     for w in (1, 16, 17, 1024, 1025, 2048):
         S = _slab(op, w)
-        for n in (3 * S - 1, 3 * S + w - 1, 4 * S + w, 5 * S + w - 2, 7 * S + w + 1):
+        for n in (2 * S + w, 3 * S - 1, 3 * S + w - 1, 4 * S + w, 5 * S + w - 2, 7 * S + w + 1,
+                  12 * S + 3):
             if n < w:
                 continue
             x = inputs.affine_pairs(n, seed + n, odd=True) if op == "affine" else \
