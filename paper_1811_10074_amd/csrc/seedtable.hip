@@ -12,18 +12,22 @@
 // ceil(bits / 8) passes, each stable, so that equal keys keep input order.
 // The entries travel through the passes as (hash, pos) when the hashes are
 // wanted in the output (the key is recomputed from the hash), else as
-// (key, pos).  A pass is three launches:
-//   1. digit histogram of each 4096-entry tile (LDS counters per wave; a
-//      digit's run in the scatter is ~16 entries long, and the tile's LDS
-//      staging -- 48 KB with hashes, 32 KB without, plus 10 KB of counters --
-//      lets two workgroups share a CU: 0.478 against 0.494 ms for 8192-entry
-//      tiles, one workgroup per CU);
-//   2. per digit, an exclusive scan over the tiles (one workgroup per digit),
-//      giving every (digit, tile) its offset inside the digit's range;
-//   3. stable scatter: a tile's entries are ranked within their digit in
+// (key, pos).  A pass is four launches:
+//   1. digit histogram of each 4096-entry tile, one 1 KB row per tile (LDS
+//      counters per wave; with hashes, passes after the first read one
+//      digit byte per entry that the previous scatter wrote, not the hash);
+//   2. the tiles split into at most 512 ranges: per range, the exclusive
+//      scan of its tiles' rows and the range's row of totals;
+//   3. per digit, the exclusive scan over the ranges' totals and the
+//      digit's total;
+//   4. stable scatter: a tile's entries are ranked within their digit in
 //      index order -- per wave, 64 consecutive entries at a time, with the
 //      lanes of equal digit found by 8 ballots -- placed in LDS in digit
 //      order, and written out as runs of consecutive addresses per digit.
+//      A digit's run in a tile is ~16 entries long; the tile's LDS staging
+//      (48 KB with hashes, 32 KB without, plus 10 KB of counters) lets two
+//      workgroups share a CU (0.478 against 0.494 ms for 8192-entry tiles,
+//      one workgroup per CU).
 // The last pass also writes the pointer table (see SeedPtrOut): its input is
 // sorted by the key bits below its digit, which lets each tile own a range of
 // pointer entries and fill it from the run of each digit in its LDS stage.
@@ -76,6 +80,12 @@ struct SeedBuffers {
     uint64_t* hash_out;
     uint32_t* key_out;
     uint32_t* pos_out;
+    // with hashes: the next pass's digit of every output entry, one byte
+    // each, written by every scatter but the last and read by the next
+    // pass's histogram (an eighth of the bytes of a hash; against a 4-byte
+    // key the extra stores in the scatter cost what the histogram saves)
+    const uint8_t* dig_in;
+    uint8_t* dig_out;
 };
 
 template <bool FIRST, bool HASH>
@@ -101,66 +111,116 @@ __device__ __forceinline__ void seed_store(const SeedBuffers& io, uint64_t d,
 
 }  // namespace
 
-// 1. digit histogram per tile: hist[d * ntiles + b]
+// 1. digit histogram per tile: hist[b * 256 + d], one coalesced 1 KB row per
+//    tile.  The first pass, and every pass without hashes, takes the digits
+//    from the keys; later passes with hashes from the digit bytes the
+//    previous scatter wrote (8 per thread, their order within the tile does
+//    not matter to a count).  One workgroup per tile:
+//    four tiles per workgroup, their loads all issued first, measured slower
+//    (too few workgroups to fill the chip).
 template <bool FIRST, bool HASH>
 __global__ __launch_bounds__(kSeedNT) void seed_hist_kernel(SeedBuffers io, uint64_t count,
                                                             uint32_t shift, uint32_t mask,
                                                             uint32_t dshift,
-                                                            uint32_t* __restrict__ hist,
-                                                            uint64_t ntiles) {
+                                                            uint32_t* __restrict__ hist) {
+    static_assert(kSeedTile == kSeedNT * 8, "eight digit bytes per thread");
     __shared__ uint32_t cnt[kSeedWaves][kDigits];
     const int lane = lane_id();
     const int wv = wave_id();
+    const uint64_t b = blockIdx.x;
+    constexpr bool kBytes = HASH && !FIRST;
+    uint32_t dig[kSeedRounds];
+    if constexpr (!kBytes) {
+#pragma unroll
+        for (int r = 0; r < kSeedRounds; ++r) {
+            const uint64_t i = b * kSeedTile + tile_slot(wv, r, lane);
+            const uint32_t k = i < count ? (FIRST ? seed_key(io.hash_in[i], shift, mask) : io.key_in[i]) : 0u;
+            dig[r] = (k >> dshift) & 0xFFu;
+        }
+    } else {
+        const uint64_t i0 = b * kSeedTile + 8ull * threadIdx.x;
+        if (i0 + 8 <= count) {
+            const uint2 v = *reinterpret_cast<const uint2*>(io.dig_in + i0);  // 8-byte aligned
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                dig[r] = (v.x >> (8 * r)) & 0xFFu;
+                dig[r + 4] = (v.y >> (8 * r)) & 0xFFu;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kSeedRounds; ++r) dig[r] = i0 + r < count ? io.dig_in[i0 + r] : 0u;
+        }
+    }
     for (int d = lane; d < kDigits; d += kWave) cnt[wv][d] = 0u;
     wave_lds_sync();
-    const uint64_t b = blockIdx.x;
-    // every load of the tile first, so that their latencies overlap
-    uint32_t key[kSeedRounds];
 #pragma unroll
     for (int r = 0; r < kSeedRounds; ++r) {
-        const uint64_t i = b * kSeedTile + tile_slot(wv, r, lane);
-        key[r] = 0u;
-        if (i < count) key[r] = (HASH || FIRST) ? seed_key(io.hash_in[i], shift, mask) : io.key_in[i];
-    }
-#pragma unroll
-    for (int r = 0; r < kSeedRounds; ++r) {
-        const uint64_t i = b * kSeedTile + tile_slot(wv, r, lane);
-        if (i < count) atomicAdd(&cnt[wv][(key[r] >> dshift) & 0xFFu], 1u);
+        const uint64_t i = kBytes ? b * kSeedTile + 8ull * threadIdx.x + (uint64_t)r
+                                  : b * kSeedTile + tile_slot(wv, r, lane);
+        if (i < count) atomicAdd(&cnt[wv][dig[r]], 1u);
     }
     __syncthreads();
     for (int d = (int)threadIdx.x; d < kDigits; d += kSeedNT) {
-        uint32_t s = 0;
+        uint32_t c = 0;
 #pragma unroll
-        for (int v = 0; v < kSeedWaves; ++v) s += cnt[v][d];
-        hist[(uint64_t)d * ntiles + b] = s;
+        for (int v = 0; v < kSeedWaves; ++v) c += cnt[v][d];
+        hist[b * kDigits + (uint64_t)d] = c;
     }
 }
 
-// 2. per digit (one workgroup each): exclusive scan of hist[d * ntiles ..]
-//    over the tiles, in place; totals[d] = the digit's count.
-__global__ __launch_bounds__(kSeedNT) void seed_scan_kernel(uint32_t* __restrict__ hist,
-                                                            uint64_t ntiles,
-                                                            uint32_t* __restrict__ totals) {
+// 2a. per range of tiles [r * per, (r + 1) * per) (one 256-thread workgroup
+//     each, thread d for digit d): hist[b * 256 + d] becomes the count of d in
+//     the range's tiles before b, and rtot[r * 256 + d] the range's count of
+//     d.  Every read and write is a coalesced 1 KB row.
+__global__ __launch_bounds__(kDigits) void seed_range_scan_kernel(uint32_t* __restrict__ hist,
+                                                                  uint64_t ntiles, uint64_t per,
+                                                                  uint32_t* __restrict__ rtot) {
+    const uint64_t d = threadIdx.x;
+    const uint64_t b0 = blockIdx.x * per;
+    const uint64_t b1 = b0 + per < ntiles ? b0 + per : ntiles;
+    uint32_t run = 0;
+    uint64_t b = b0;
+    for (; b + 4 <= b1; b += 4) {  // four independent loads in flight
+        uint32_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = hist[(b + q) * kDigits + d];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            hist[(b + q) * kDigits + d] = run;
+            run += v[q];
+        }
+    }
+    for (; b < b1; ++b) {
+        const uint32_t v = hist[b * kDigits + d];
+        hist[b * kDigits + d] = run;
+        run += v;
+    }
+    rtot[blockIdx.x * kDigits + d] = run;
+}
+
+// 2b. per digit d (one workgroup each, one range per thread, at most
+//     kSeedNT ranges): rtot[r * 256 + d] becomes the count of d in the
+//     ranges before r, and totals[d] the digit's count.
+__global__ __launch_bounds__(kSeedNT) void seed_range_base_kernel(uint32_t* __restrict__ rtot,
+                                                                  uint64_t nranges,
+                                                                  uint32_t* __restrict__ totals) {
     __shared__ uint32_t part[kSeedWaves];
     const int lane = lane_id();
     const int wv = wave_id();
-    uint32_t* row = hist + (uint64_t)blockIdx.x * ntiles;
-    uint32_t carry = 0;
-    for (uint64_t base = 0; base < ntiles; base += kSeedNT) {
-        const uint64_t i = base + threadIdx.x;
-        const uint32_t v = i < ntiles ? row[i] : 0u;
-        uint32_t incl = wave_inclusive_sum(v);
-        if (lane == kWave - 1) part[wv] = incl;
-        __syncthreads();
-        uint32_t before = carry;
-        for (int v2 = 0; v2 < wv; ++v2) before += part[v2];
-        uint32_t chunk = 0;
-        for (int v2 = 0; v2 < kSeedWaves; ++v2) chunk += part[v2];
-        if (i < ntiles) row[i] = before + incl - v;
-        carry += chunk;
-        __syncthreads();
+    const uint64_t d = blockIdx.x;
+    const uint64_t r = threadIdx.x;
+    const uint32_t v = r < nranges ? rtot[r * kDigits + d] : 0u;
+    const uint32_t incl = wave_inclusive_sum(v);
+    if (lane == kWave - 1) part[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kSeedWaves; ++w2) {
+        before += w2 < wv ? part[w2] : 0u;
+        all += part[w2];
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    if (r < nranges) rtot[r * kDigits + d] = before + incl - v;
+    if (threadIdx.x == 0) totals[d] = all;
 }
 
 // Exclusive scan of 256 values held one per lane-slot (v[c + lane], c in
@@ -203,8 +263,8 @@ struct SeedPtrOut {
 template <bool FIRST, bool HASH, bool LAST>
 __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
     SeedBuffers io, uint64_t count, uint32_t shift, uint32_t mask, uint32_t dshift,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, uint64_t ntiles,
-    uint32_t per_xcd, SeedPtrOut po) {
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ rtot, uint64_t per,
+    const uint32_t* __restrict__ totals, uint64_t ntiles, uint32_t per_xcd, SeedPtrOut po) {
     __shared__ uint32_t cnt[kSeedWaves][kDigits];  // running counts, then wave offsets
     __shared__ uint32_t gbase[kDigits];            // global start of the tile's run of d
     __shared__ uint32_t tstart[kDigits];           // start of d in the tile's digit order
@@ -221,13 +281,18 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
     const int lane = lane_id();
     const int wv = wave_id();
     for (int d = lane; d < kDigits; d += kWave) cnt[wv][d] = 0u;
-    if (wv == 0) {
-        for (int d = lane; d < kDigits; d += kWave) gbase[d] = totals[d];
-        wave_lds_sync();
-        wave_scan256(gbase, lane);  // digit starts
-        for (int d = lane; d < kDigits; d += kWave) gbase[d] += hist[(uint64_t)d * ntiles + b];
-    }
     wave_lds_sync();
+    // Thread d < 256: digit d's total and the count of d in earlier tiles
+    // (earlier ranges, then the range's tiles before b), loaded now into
+    // registers and used only after the ranking rounds, so that no wave waits
+    // on them before it ranks.
+    const int tid = (int)threadIdx.x;
+    uint32_t d_total = 0, d_range = 0, d_tile = 0;
+    if (tid < kDigits) {
+        d_total = totals[tid];
+        d_range = rtot[(b / per) * kDigits + (uint64_t)tid];
+        d_tile = hist[b * kDigits + (uint64_t)tid];
+    }
     const uint64_t below = (1ull << lane) - 1ull;
     // LAST: the low parts of the previous tile's last entry and of this tile's
     // last entry bound this tile's pointer entries; loaded early
@@ -269,8 +334,10 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
         wave_lds_sync();
     }
     __syncthreads();
-    // per digit: wave offsets (exclusive over waves) and the tile's digit total
-    for (int d = (int)threadIdx.x; d < kDigits; d += kSeedNT) {
+    // per digit: wave offsets (exclusive over waves), the tile's digit total
+    // and the digit's total over all tiles
+    if (tid < kDigits) {
+        const int d = tid;
         uint32_t run = 0;
 #pragma unroll
         for (int v = 0; v < kSeedWaves; ++v) {
@@ -279,10 +346,14 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
             run += t;
         }
         tstart[d] = run;
+        gbase[d] = d_total;
     }
     __syncthreads();
-    if (wv == 0) wave_scan256(tstart, lane);
+    if (wv == 0) wave_scan256(tstart, lane);  // starts of the digits in the tile's order
+    if (wv == 1) wave_scan256(gbase, lane);   // starts of the digits in the output
     __syncthreads();
+    // global start of the tile's run of d (read only after the next barrier)
+    if (tid < kDigits) gbase[tid] += d_range + d_tile;
     // place the tile in digit order
 #pragma unroll
     for (int r = 0; r < kSeedRounds; ++r) {
@@ -303,8 +374,11 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
         if constexpr (HASH) it.h = stage_h[t];
         else it.k = stage_k[t];
         it.p = stage_p[t];
-        const uint32_t d = (it.key(shift, mask) >> dshift) & 0xFFu;
-        seed_store<HASH>(io, (uint64_t)gbase[d] + (t - tstart[d]), it);
+        const uint32_t k = it.key(shift, mask);
+        const uint32_t d = (k >> dshift) & 0xFFu;
+        const uint64_t dst = (uint64_t)gbase[d] + (t - tstart[d]);
+        seed_store<HASH>(io, dst, it);
+        if constexpr (HASH && !LAST) io.dig_out[dst] = (uint8_t)((k >> (dshift + 8u)) & 0xFFu);
     }
     if constexpr (LAST) {
         // this tile's pointer entries: low values vlo .. vhi of every digit
@@ -384,38 +458,55 @@ uint64_t seed_tiles(uint64_t count) { return (count + kSeedTile - 1) / kSeedTile
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
+// Ranges of tiles of the offset scan: at most one per thread of the range
+// base kernel.
+uint64_t seed_ranges(uint64_t nt) { return nt < (uint64_t)kSeedNT ? nt : (uint64_t)kSeedNT; }
+
+// The offset arrays of a pass.
+struct SeedOffsets {
+    uint32_t* hist;    // [tile * 256 + d]
+    uint32_t* rtot;    // [range * 256 + d]
+    uint32_t* totals;  // [d]
+};
+
 template <bool FIRST, bool HASH, bool LAST>
 void seed_pass(const SeedBuffers& io, uint64_t count, uint32_t shift, uint32_t mask,
-               uint32_t dshift, uint32_t* hist, uint32_t* totals, uint64_t nt,
-               const SeedPtrOut& po, hipStream_t s) {
+               uint32_t dshift, const SeedOffsets& off, uint64_t nt, const SeedPtrOut& po,
+               hipStream_t s) {
+    const uint64_t nr = seed_ranges(nt), per = (nt + nr - 1) / nr;
     hipLaunchKernelGGL((seed_hist_kernel<FIRST, HASH>), dim3((unsigned)nt), dim3(kSeedNT), 0, s,
-                       io, count, shift, mask, dshift, hist, nt);
-    hipLaunchKernelGGL(seed_scan_kernel, dim3(kDigits), dim3(kSeedNT), 0, s, hist, nt, totals);
+                       io, count, shift, mask, dshift, off.hist);
+    hipLaunchKernelGGL(seed_range_scan_kernel, dim3((unsigned)((nt + per - 1) / per)),
+                       dim3(kDigits), 0, s, off.hist, nt, per, off.rtot);
+    hipLaunchKernelGGL(seed_range_base_kernel, dim3(kDigits), dim3(kSeedNT), 0, s, off.rtot,
+                       (nt + per - 1) / per, off.totals);
     const uint32_t per_xcd = (uint32_t)((nt + kXcds - 1) / kXcds);
     hipLaunchKernelGGL((seed_scatter_kernel<FIRST, HASH, LAST>), dim3(per_xcd * kXcds),
-                       dim3(kSeedNT), 0, s, io, count, shift, mask, dshift, hist, totals, nt,
-                       per_xcd, po);
+                       dim3(kSeedNT), 0, s, io, count, shift, mask, dshift, off.hist, off.rtot,
+                       per, off.totals, nt, per_xcd, po);
 }
 
 template <bool HASH>
 void seed_pass_any(bool first, bool last, const SeedBuffers& io, uint64_t count, uint32_t shift,
-                   uint32_t mask, uint32_t dshift, uint32_t* hist, uint32_t* totals, uint64_t nt,
+                   uint32_t mask, uint32_t dshift, const SeedOffsets& off, uint64_t nt,
                    const SeedPtrOut& po, hipStream_t s) {
-    if (first && last) seed_pass<true, HASH, true>(io, count, shift, mask, dshift, hist, totals, nt, po, s);
-    else if (first) seed_pass<true, HASH, false>(io, count, shift, mask, dshift, hist, totals, nt, po, s);
-    else if (last) seed_pass<false, HASH, true>(io, count, shift, mask, dshift, hist, totals, nt, po, s);
-    else seed_pass<false, HASH, false>(io, count, shift, mask, dshift, hist, totals, nt, po, s);
+    if (first && last) seed_pass<true, HASH, true>(io, count, shift, mask, dshift, off, nt, po, s);
+    else if (first) seed_pass<true, HASH, false>(io, count, shift, mask, dshift, off, nt, po, s);
+    else if (last) seed_pass<false, HASH, true>(io, count, shift, mask, dshift, off, nt, po, s);
+    else seed_pass<false, HASH, false>(io, count, shift, mask, dshift, off, nt, po, s);
 }
 
 }  // namespace
 
 // Workspace: two carries of (8-byte hash or 4-byte key, 4-byte position),
-// the digit-major tile histogram and the 256 digit totals.
+// the tile histogram rows, the range counts, the 256 digit totals and the
+// digit bytes.
 uint64_t seed_table_workspace_bytes(uint64_t count, uint32_t bits) {
     (void)bits;
     const uint64_t nt = seed_tiles(count);
     return 2 * align256(8 * count) + 2 * align256(4 * count) + align256(4ull * kDigits * nt) +
-           align256(4ull * kDigits);
+           align256(4ull * kDigits * seed_ranges(nt)) + align256(4ull * kDigits) +
+           align256(count);
 }
 
 int launch_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count, uint32_t bits,
@@ -430,9 +521,11 @@ int launch_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count,
     uint8_t* wp = ws + 2 * align256(8 * count);
     uint32_t* carryP[2] = {reinterpret_cast<uint32_t*>(wp),
                            reinterpret_cast<uint32_t*>(wp + align256(4 * count))};
-    uint32_t* hist = reinterpret_cast<uint32_t*>(wp + 2 * align256(4 * count));
-    uint32_t* totals = reinterpret_cast<uint32_t*>(wp + 2 * align256(4 * count) +
-                                                   align256(4ull * kDigits * nt));
+    SeedOffsets off;
+    off.hist = reinterpret_cast<uint32_t*>(wp + 2 * align256(4 * count));
+    off.rtot = off.hist + align256(4ull * kDigits * nt) / 4;
+    off.totals = off.rtot + align256(4ull * kDigits * seed_ranges(nt)) / 4;
+    uint8_t* digits = reinterpret_cast<uint8_t*>(off.totals) + align256(4ull * kDigits);
     const bool with_hash = hash_out != nullptr;
     if (count == 0) {
         // no entries: every pointer is 0
@@ -449,6 +542,10 @@ int launch_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count,
     SeedBuffers io{};
     io.hash_in = hash;
     io.pos_in = pos;
+    // one digit buffer serves every pass: a pass's histogram has read it
+    // before its scatter writes the next pass's digits
+    io.dig_in = digits;
+    io.dig_out = digits;
     for (int p = 0; p < passes; ++p) {
         const bool last = p == passes - 1;
         const int o = p & 1;
@@ -458,9 +555,9 @@ int launch_seed_table(const uint64_t* hash, const uint32_t* pos, uint64_t count,
         else io.key_out = reinterpret_cast<uint32_t*>(carryH[o]);  // keys in the hash slots
         const uint32_t dshift = 8u * (uint32_t)p;
         if (with_hash)
-            seed_pass_any<true>(p == 0, last, io, count, shift, mask, dshift, hist, totals, nt, po, s);
+            seed_pass_any<true>(p == 0, last, io, count, shift, mask, dshift, off, nt, po, s);
         else
-            seed_pass_any<false>(p == 0, last, io, count, shift, mask, dshift, hist, totals, nt, po, s);
+            seed_pass_any<false>(p == 0, last, io, count, shift, mask, dshift, off, nt, po, s);
         // this pass's outputs are the next pass's inputs
         io.pos_in = io.pos_out;
         if (with_hash) io.hash_in = io.hash_out;
