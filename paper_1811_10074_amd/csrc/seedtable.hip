@@ -101,13 +101,6 @@ __device__ __forceinline__ SeedItem<HASH> seed_load(const SeedBuffers& io, uint6
     return it;
 }
 
-template <bool HASH>
-__device__ __forceinline__ void seed_store(const SeedBuffers& io, uint64_t d,
-                                           const SeedItem<HASH>& it) {
-    if constexpr (HASH) io.hash_out[d] = it.h;
-    else io.key_out[d] = it.k;
-    io.pos_out[d] = it.p;
-}
 
 }  // namespace
 
@@ -268,10 +261,13 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
     __shared__ uint32_t cnt[kSeedWaves][kDigits];  // running counts, then wave offsets
     __shared__ uint32_t gbase[kDigits];            // global start of the tile's run of d
     __shared__ uint32_t tstart[kDigits];           // start of d in the tile's digit order
-    // the tile in digit order, field by field (no padding)
+    // the tile in digit order, field by field (no padding).  With hashes the
+    // positions follow the hashes through the same 32 KB (42 KB per
+    // workgroup instead of 58: three workgroups per CU instead of two).
     __shared__ uint64_t stage_h[HASH ? kSeedTile : 1];
     __shared__ uint32_t stage_k[HASH ? 1 : kSeedTile];
-    __shared__ uint32_t stage_p[kSeedTile];
+    __shared__ uint32_t stage_p_own[HASH ? 1 : kSeedTile];
+    uint32_t* const stage_p = HASH ? reinterpret_cast<uint32_t*>(stage_h) : stage_p_own;
     // Workgroups are dealt to the dies round-robin; each die takes a
     // contiguous run of tiles, so that the line a tile's run of a digit (or of
     // pointer entries) leaves partly written is completed by the next tile in
@@ -354,31 +350,44 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
     __syncthreads();
     // global start of the tile's run of d (read only after the next barrier)
     if (tid < kDigits) gbase[tid] += d_range + d_tile;
-    // place the tile in digit order
+    // place the tile in digit order (with hashes, the hashes only; the
+    // slots are kept for the positions)
+    uint32_t slot[kSeedRounds];
 #pragma unroll
     for (int r = 0; r < kSeedRounds; ++r) {
         const uint64_t i = b * kSeedTile + tile_slot(wv, r, lane);
+        slot[r] = 0u;
         if (i >= count) continue;
         const uint32_t d = (item[r].key(shift, mask) >> dshift) & 0xFFu;
-        const uint32_t slot = tstart[d] + cnt[wv][d] + rank[r];
-        if constexpr (HASH) stage_h[slot] = item[r].h;
-        else stage_k[slot] = item[r].k;
-        stage_p[slot] = item[r].p;
+        slot[r] = tstart[d] + cnt[wv][d] + rank[r];
+        if constexpr (HASH) {
+            stage_h[slot[r]] = item[r].h;
+        } else {
+            stage_k[slot[r]] = item[r].k;
+            stage_p[slot[r]] = item[r].p;
+        }
     }
     __syncthreads();
     // write out: consecutive slots of one digit go to consecutive addresses
     const uint64_t t0 = b * kSeedTile;
     const uint32_t nb = count - t0 < kSeedTile ? (uint32_t)(count - t0) : kSeedTile;
-    for (uint32_t t = threadIdx.x; t < nb; t += kSeedNT) {
-        SeedItem<HASH> it;
-        if constexpr (HASH) it.h = stage_h[t];
-        else it.k = stage_k[t];
-        it.p = stage_p[t];
-        const uint32_t k = it.key(shift, mask);
+    uint32_t dst_of[kSeedRounds];  // HASH: where slot threadIdx.x + j * kSeedNT goes
+#pragma unroll
+    for (int j = 0; j < kSeedRounds; ++j) {
+        const uint32_t t = threadIdx.x + (uint32_t)j * kSeedNT;
+        dst_of[j] = 0u;
+        if (t >= nb) continue;
+        const uint32_t k = HASH ? seed_key(stage_h[t], shift, mask) : stage_k[t];
         const uint32_t d = (k >> dshift) & 0xFFu;
-        const uint64_t dst = (uint64_t)gbase[d] + (t - tstart[d]);
-        seed_store<HASH>(io, dst, it);
-        if constexpr (HASH && !LAST) io.dig_out[dst] = (uint8_t)((k >> (dshift + 8u)) & 0xFFu);
+        const uint32_t dst = gbase[d] + (t - tstart[d]);  // < count < 2^32
+        if constexpr (HASH) {
+            io.hash_out[dst] = stage_h[t];
+            if constexpr (!LAST) io.dig_out[dst] = (uint8_t)((k >> (dshift + 8u)) & 0xFFu);
+            dst_of[j] = dst;
+        } else {
+            io.key_out[dst] = k;
+            io.pos_out[dst] = stage_p[t];
+        }
     }
     if constexpr (LAST) {
         // this tile's pointer entries: low values vlo .. vhi of every digit
@@ -440,6 +449,21 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
             }
         }
         if (b + 1 == ntiles && threadIdx.x == 0) po.ptr[po.nkeys] = (uint32_t)count;
+    }
+    if constexpr (HASH) {
+        // the positions, through the region the hashes have left
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSeedRounds; ++r) {
+            const uint64_t i = b * kSeedTile + tile_slot(wv, r, lane);
+            if (i < count) stage_p[slot[r]] = item[r].p;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSeedRounds; ++j) {
+            const uint32_t t = threadIdx.x + (uint32_t)j * kSeedNT;
+            if (t < nb) io.pos_out[dst_of[j]] = stage_p[t];
+        }
     }
 }
 
