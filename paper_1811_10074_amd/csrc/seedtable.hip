@@ -24,10 +24,10 @@
 //      index order -- per wave, 64 consecutive entries at a time, with the
 //      lanes of equal digit found by 8 ballots -- placed in LDS in digit
 //      order, and written out as runs of consecutive addresses per digit.
-//      A digit's run in a tile is ~16 entries long; the tile's LDS staging
-//      (48 KB with hashes, 32 KB without, plus 10 KB of counters) lets two
-//      workgroups share a CU (0.478 against 0.494 ms for 8192-entry tiles,
-//      one workgroup per CU).
+//      A digit's run in a tile is ~16 entries long.  The tile's LDS staging
+//      is 32 KB either way (with hashes, the positions pass through the
+//      region after the hashes have left it), plus 10 KB of counters: 43,008
+//      bytes per workgroup, three workgroups per CU.
 // The last pass also writes the pointer table (see SeedPtrOut): its input is
 // sorted by the key bits below its digit, which lets each tile own a range of
 // pointer entries and fill it from the run of each digit in its LDS stage.
