@@ -20,6 +20,7 @@ import json
 import os
 import platform
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -402,16 +403,32 @@ def bench_serve(torch, quick):
             for f in [srv.submit(sq, of) for _, sq, of in reqs[:2000]]:
                 f.result(timeout=600)
         srv.completed.clear()
+        # the client consumes each result as it arrives (counts it and lets it
+        # go) instead of holding every result of the run
+        left = [len(reqs)]
+        errors = []
+        finished = threading.Event()
+        count_lock = threading.Lock()
+
+        def consumed(f):
+            if f.exception() is not None:
+                errors.append(f.exception())
+            with count_lock:
+                left[0] -= 1
+                if left[0] == 0:
+                    finished.set()
+
         t0 = time.perf_counter()
-        futs = []
         for t, sq, of in reqs:
             if open_loop:
                 d = t0 + t - time.perf_counter()
                 if d > 0:
                     time.sleep(d)
-            futs.append(srv.submit(sq, of))
-        for f in futs:
-            f.result(timeout=600)
+            srv.submit(sq, of).add_done_callback(consumed)
+        if not finished.wait(600):
+            raise RuntimeError("serving run did not finish within 600 s")
+        if errors:
+            raise errors[0]
         wall = time.perf_counter() - t0
         srv.stop()
         st = latency_stats(srv.completed)

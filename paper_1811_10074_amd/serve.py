@@ -725,6 +725,16 @@ class Server:
                     for q in reqs:
                         q.solo = True
                     retry = reqs
+            if not retry:
+                # a resolved request keeps its timings only: its future (and
+                # through it the result) and its bases belong to the client
+                # now, and are freed when the client lets them go rather than
+                # when the server stops (a client that drops each result lets
+                # the next batch's result arrays reuse that memory instead of
+                # faulting in fresh pages)
+                for q in reqs:
+                    q.future = None
+                    q.seqs = None
             with self.state_lock:
                 self.arena.release(slot, nbytes)
                 self.inflight.remove(item)
