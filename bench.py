@@ -446,6 +446,17 @@ def bench_serve(torch, quick):
     return out
 
 
+# the sliding-sum workloads --profile runs: (op, w, n, path)
+SLIDING_PROFILES = {
+    "sliding": ("add", 16, 1 << 28, "generic"),
+    "affine1024": ("affine", 1024, 1 << 28, "auto"),
+    "config1": ("min", 16, 1 << 20, "auto"),
+    "add1024": ("add", 1024, 1 << 28, "auto"),
+    "minlog64": ("min", 64, 1 << 28, "log"),
+    "scalar16": ("add", 16, 1 << 28, "scalar"),
+}
+
+
 def profile_run(torch, args):
     """A plain device copy of exactly 1 GiB (its FETCH_SIZE / WRITE_SIZE
     calibrate the counters), then the kernel under study."""
@@ -466,10 +477,8 @@ def profile_run(torch, args):
         r = sws.MinimizerRunner(n, 15, 10)
         ms, med, _ = time_launches(torch, lambda: r.launch(seq=seq), args.steps, args.warmup)
         print(json.dumps({"kernel": "minimizer", "ms_per_step": ms, "count": int(r.count.item())}))
-    elif args.profile in ("sliding", "affine1024", "config1"):
-        op, w, n, path = {"sliding": ("add", 16, 1 << 28, "generic"),
-                          "affine1024": ("affine", 1024, 1 << 28, "auto"),
-                          "config1": ("min", 16, 1 << 20, "auto")}[args.profile]
+    elif args.profile in SLIDING_PROFILES:
+        op, w, n, path = SLIDING_PROFILES[args.profile]
         x = inputs.affine_pairs(n, seed=2) if op == "affine" else \
             inputs.uniform_u32(n, seed=0 if n == 1 << 20 else 2)
         x = torch.from_numpy(x.view(np.int32)).cuda()
@@ -506,8 +515,7 @@ def main():
     ap.add_argument("--primary-only", action="store_true",
                     help="only the timed minimizer steps (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile", choices=["minimizer", "sliding", "affine1024", "config1",
-                                          "seedtable", "batch"],
+    ap.add_argument("--profile", choices=["minimizer", "seedtable", "batch"] + list(SLIDING_PROFILES),
                     help="run only a 1-GiB plain copy (counter calibration) and the named kernel "
                          "--steps times, for rocprofv3")
     args = ap.parse_args()
