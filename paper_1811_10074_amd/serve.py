@@ -654,41 +654,58 @@ class Server:
             self.queued_bases -= nb
         return reqs, slot, need
 
+    def _collect_finished(self) -> bool:
+        """Hands finished batches to the completer; True if any."""
+        progressed = False
+        with self.state_lock:
+            for item in self.inflight:
+                if not item[4] and self.ex.done(item[0]):
+                    item[4] = True
+                    self.done_q.append(item)
+                    self.done_wake.set()
+                    progressed = True
+        return progressed
+
+    def _start_batch(self) -> Optional[bool]:
+        """Forms and starts one batch: True if it started, False if its start
+        failed (its requests have the error), None if no batch could form."""
+        b = self._form_batch()
+        if b is None:
+            return None
+        reqs, slot, need = b
+        now = time.perf_counter()
+        for q in reqs:
+            q.admitted = now
+        try:
+            handle = self.ex.start(reqs, slot)
+        except Exception as exc:
+            with self.state_lock:
+                self.arena.release(slot, need)
+            for q in reqs:
+                q.future.set_exception(exc)
+            return False
+        with self.state_lock:
+            self.inflight.append([handle, slot, need, reqs, False])
+        return True
+
     def _loop(self):
         """Scheduler: hands finished batches to the completer and admits new
-        ones while streams and arena bytes allow."""
+        ones while streams and arena bytes allow.  (The work is done in
+        helpers, so that no batch stays referenced from this frame while it
+        waits.)"""
         while not self.stop_flag:
-            progressed = False
+            progressed = self._collect_finished()
             with self.state_lock:
-                for item in self.inflight:
-                    if not item[4] and self.ex.done(item[0]):
-                        item[4] = True
-                        self.done_q.append(item)
-                        self.done_wake.set()
-                        progressed = True
                 busy = len(self.inflight)
             while busy < self.ex.slots() and self.queue:
                 if busy > 0 and self.queued_bases < self.concurrent_bases:
                     break
-                b = self._form_batch()
-                if b is None:
+                started = self._start_batch()
+                if started is None:
                     break
-                reqs, slot, need = b
-                now = time.perf_counter()
-                for q in reqs:
-                    q.admitted = now
-                try:
-                    handle = self.ex.start(reqs, slot)
-                except Exception as exc:
-                    with self.state_lock:
-                        self.arena.release(slot, need)
-                    for q in reqs:
-                        q.future.set_exception(exc)
-                    continue
-                with self.state_lock:
-                    self.inflight.append([handle, slot, need, reqs, False])
-                busy += 1
-                progressed = True
+                if started:
+                    busy += 1
+                    progressed = True
             if not progressed:
                 if not self.inflight and not self.queue:
                     self.wake.wait(0.01)
@@ -709,42 +726,46 @@ class Server:
                 self.done_wake.wait(0.01)
                 self.done_wake.clear()
                 continue
-            item = self.done_q.popleft()
-            handle, slot, nbytes, reqs, _ = item
-            retry = []
-            try:
-                results = self.ex.finish(handle)
-                now = time.perf_counter()
-                for q, r in zip(reqs, results):
-                    q.finished = now
-                    q.future.set_result(r)
-            except Exception as exc:
-                if len(reqs) == 1:
-                    reqs[0].future.set_exception(exc)
-                else:
-                    for q in reqs:
-                        q.solo = True
-                    retry = reqs
-            if not retry:
-                # a resolved request keeps its timings only: its future (and
-                # through it the result) and its bases belong to the client
-                # now, and are freed when the client lets them go rather than
-                # when the server stops (a client that drops each result lets
-                # the next batch's result arrays reuse that memory instead of
-                # faulting in fresh pages)
-                for q in reqs:
-                    q.future = None
-                    q.seqs = None
-            with self.state_lock:
-                self.arena.release(slot, nbytes)
-                self.inflight.remove(item)
-                if not retry:
-                    self.completed.extend(reqs)
-            if retry:
-                with self.lock:
-                    self.queue.extendleft(reversed(retry))
-                    self.queued_bases += sum(q.nbases for q in retry)
+            self._complete(self.done_q.popleft())
             self.wake.set()
+
+    def _complete(self, item):
+        """One finished batch.  (A method of its own, so that nothing of the
+        batch stays referenced from the completer's frame afterwards.)"""
+        handle, slot, nbytes, reqs, _ = item
+        retry = []
+        try:
+            results = self.ex.finish(handle)
+            now = time.perf_counter()
+            for q, r in zip(reqs, results):
+                q.finished = now
+                q.future.set_result(r)
+        except Exception as exc:
+            if len(reqs) == 1:
+                reqs[0].future.set_exception(exc)
+            else:
+                for q in reqs:
+                    q.solo = True
+                retry = reqs
+        if not retry:
+            # a resolved request keeps its timings only: its future (and
+            # through it the result) and its bases belong to the client now,
+            # and are freed when the client lets them go rather than when the
+            # server stops (a client that drops each result lets the next
+            # batch's result arrays reuse that memory instead of faulting in
+            # fresh pages)
+            for q in reqs:
+                q.future = None
+                q.seqs = None
+        with self.state_lock:
+            self.arena.release(slot, nbytes)
+            self.inflight.remove(item)
+            if not retry:
+                self.completed.extend(reqs)
+        if retry:
+            with self.lock:
+                self.queue.extendleft(reversed(retry))
+                self.queued_bases += sum(q.nbases for q in retry)
 
 
 def latency_stats(reqs: List[Request]):

@@ -2,7 +2,9 @@
 admission by arena bytes, oldest-first order, overlap of in-flight batches,
 per-request failure isolation, oversize rejection, and identical results
 alone and in a mix."""
+import gc
 import time
+import weakref
 
 import numpy as np
 import pytest
@@ -149,3 +151,24 @@ def test_concurrency_follows_the_queue():
         srv.stop()
         assert all(same(r, expected(*q)) for r, q in zip(res, reqs))
         assert (ex.max_inflight_seen >= 2) == overlap, (thr, ex.max_inflight_seen)
+
+
+def test_results_not_retained():
+    """Once the client lets a result go, nothing in the server keeps it (or
+    the request's bases) alive: a long-running server does not accumulate
+    what it has handed out, and freed result memory is reused."""
+    srv = Server(FakeExecutor(K, W, compute=oracle_compute), K, W).start()
+    seqs, off = make_request(700)
+    f = srv.submit(seqs, off)
+    res = f.result(timeout=30)
+    ok = same(res, expected(seqs, off))  # (an assert's rewritten temporaries would hold res)
+    assert ok
+    ref_res, ref_seqs = weakref.ref(res), weakref.ref(seqs)
+    del f, res, seqs
+    time.sleep(0.05)  # the completer finishes its round
+    gc.collect()
+    assert ref_res() is None, "the server still holds a result the client dropped"
+    assert ref_seqs() is None, "the server still holds a completed request's bases"
+    # its timings stay for the latency statistics
+    assert latency_stats(srv.completed)["n"] == 1
+    srv.stop()
