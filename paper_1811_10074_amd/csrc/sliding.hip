@@ -96,6 +96,7 @@ struct SlabIO {
     // Chunks below nchunks of the slab at element p0 (wholly below n), the
     // rest as the identity: the slab after a wave's last one is needed only
     // up to its first w - 1 elements.
+    template <bool NT = true>
     static __device__ __forceinline__ void load_head(const T* __restrict__ x, uint64_t p0, int lane,
                                                      uint32_t nchunks, T ident,
                                                      u32x4 (&raw)[kChunks]) {
@@ -108,9 +109,8 @@ struct SlabIO {
 #pragma unroll
         for (int i = 0; i < kChunks; ++i) {
             const uint32_t c = (uint32_t)(i * kWave + lane);
-            raw[i] = c < nchunks ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(
-                                       x + p0 + (uint64_t)c * per))
-                                 : id;
+            const u32x4* src = reinterpret_cast<const u32x4*>(x + p0 + (uint64_t)c * per);
+            raw[i] = c < nchunks ? (NT ? __builtin_nontemporal_load(src) : *src) : id;
         }
     }
 
@@ -186,7 +186,7 @@ __host__ __device__ constexpr uint32_t ring_rows(uint32_t w) {
 // y_i = P_{i+w-1} - P_{i-1} with P a running prefix local to the wave (an
 // offset common to both terms cancels).  The ring then holds P, the suffix
 // registers hold the exclusive prefix, and the segment masks are unused.
-template <class Op, int R, int WAVES, bool PFX = false>
+template <class Op, int R, int WAVES, bool PFX = false, bool EARLY_HALO = false>
 __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
     const typename Op::T* __restrict__ x, uint64_t n, uint32_t w, typename Op::T* __restrict__ y,
     uint64_t count, uint64_t total_slabs, uint64_t slabs_per_wave, int vec, uint32_t rows) {
@@ -218,6 +218,22 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
     const HeadMask<R> pat = head_pattern<R>(w);
     const T ident = Op::identity();
     const bool v16 = vec != 0;
+
+    // Which steps run unchecked (see the loop at the end): the step that
+    // prefetches the next wave's first slab (MODE 3) runs when the wave has
+    // two slabs or more and both bounds reach its last slab.
+    const uint64_t by_count = count / S;  // s + 1 <= count / S: outputs in range
+    const uint64_t by_n = n / S >= 3 ? n / S - 2 : 0;  // s + 3 <= n / S
+    const bool mode3 = v16 && s0 + 2 <= s1 && by_n >= s1 - 1 && by_count >= s1 - 1;
+    // EARLY_HALO: that slab's first w - 1 elements (this wave's halo) are
+    // loaded now, through the caches, while the next wave (the workgroup's
+    // other wave, or the next workgroup's first) loads the same lines as its
+    // first slab, rather than at this wave's end, when they have long left
+    // the caches.  They wait in registers (16 VGPRs at R = 16).
+    u32x4 halo[EARLY_HALO ? IO::kChunks : 1];
+    if constexpr (EARLY_HALO) {
+        if (mode3) IO::template load_head<false>(x, s1 * (uint64_t)S, lane, head_chunks, ident, halo);
+    }
 
     // slab A = s0: prefix sums into ring half 0, suffix sums in registers
     uint32_t mA = (uint32_t)((s0 * (uint64_t)S) % w);
@@ -272,8 +288,14 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
             // prefetch slab s + 2 while B and A are computed
             if (MODE == 0)
                 IO::template load<false>(x, n, baseA + 2 * (uint64_t)S, lane, v16, ident, raw);
-            else if (MODE == 3)
-                IO::load_head(x, baseA + 2 * (uint64_t)S, lane, head_chunks, ident, raw);
+            else if (MODE == 3) {
+                if constexpr (EARLY_HALO) {
+#pragma unroll
+                    for (int i = 0; i < IO::kChunks; ++i) raw[i] = halo[i];
+                } else {
+                    IO::load_head(x, baseA + 2 * (uint64_t)S, lane, head_chunks, ident, raw);
+                }
+            }
             else if (MODE == 2 && s + 1 < s1)
                 IO::template load<true>(x, s + 2 == s1 ? halo_n : n, baseA + 2 * (uint64_t)S,
                                         lane, v16, ident, raw);
@@ -344,10 +366,8 @@ __global__ __launch_bounds__(WAVES * kWave) void sliding_generic_kernel(
     using M1 = std::integral_constant<int, 1>;
     using M2 = std::integral_constant<int, 2>;
     using M3 = std::integral_constant<int, 3>;
-    const uint64_t by_count = count / S;  // s + 1 <= count / S: outputs in range
     uint64_t s = s0;
     if (v16) {
-        const uint64_t by_n = n / S >= 3 ? n / S - 2 : 0;  // s + 3 <= n / S
         uint64_t pf_end = by_n < by_count ? by_n : by_count;
         if (pf_end > s1 - 1) pf_end = s1 - 1;
         if (s < pf_end) {
@@ -825,8 +845,14 @@ int launch_sliding_scalar(int op, const void* x, uint64_t n, uint32_t w, void* y
 // Launchers.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kDefaultSlidingWaves = 256ull * 128ull;  // 128 per compute unit
+// Windows from this length load their halo early (EARLY_HALO).  At n = 2^28:
+// + (the prefix-difference form) 0.675 -> 0.74 of HBM peak at w = 1024 and
+// 0.69 -> 0.73 at w = 768; min and max at w <= 1024 unchanged (not bound by
+// the halo), so is w <= 512.  Four waves per workgroup (more neighbours
+// sharing a CU) measured no better than two.
+constexpr uint32_t kEarlyHaloMinW = 512;
 
-template <class Op, int R, int WAVES, bool PFX = false>
+template <class Op, int R, int WAVES, bool PFX = false, bool EARLY_HALO = false>
 static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
                           uint64_t target_waves, hipStream_t s) {
     using T = typename Op::T;
@@ -840,7 +866,7 @@ static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64
     const int vec = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0 ? 1 : 0;
     const uint32_t rows = ring_rows<R>(w);
     const size_t lds = (size_t)WAVES * rows * (R + 1) * sizeof(T);
-    hipLaunchKernelGGL((sliding_generic_kernel<Op, R, WAVES, PFX>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((sliding_generic_kernel<Op, R, WAVES, PFX, EARLY_HALO>), dim3((unsigned)blocks),
                        dim3(WAVES * kWave), lds, s, static_cast<const T*>(x), n, w,
                        static_cast<T*>(y), count, total_slabs, spw, vec, rows);
     return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -884,12 +910,16 @@ int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* 
     if (tw == 0) tw = (op == kOpAffine && w <= 512u) ? 2 * kDefaultSlidingWaves : kDefaultSlidingWaves;
     // <Op, R, waves per workgroup>
     const bool big = w > (uint32_t)(kWave * 16);
+    const bool early = w >= kEarlyHaloMinW;
     switch (op) {
     case kOpAdd: return big ? launch_generic<OpAdd, 32, 1>(x, n, w, y, count, tw, s)
+                     : early ? launch_generic<OpAdd, 16, 2, false, true>(x, n, w, y, count, tw, s)
                             : launch_generic<OpAdd, 16, 2>(x, n, w, y, count, tw, s);
     case kOpMin: return big ? launch_generic<OpMin, 32, 1>(x, n, w, y, count, tw, s)
+                     : early ? launch_generic<OpMin, 16, 2, false, true>(x, n, w, y, count, tw, s)
                             : launch_generic<OpMin, 16, 2>(x, n, w, y, count, tw, s);
     case kOpMax: return big ? launch_generic<OpMax, 32, 1>(x, n, w, y, count, tw, s)
+                     : early ? launch_generic<OpMax, 16, 2, false, true>(x, n, w, y, count, tw, s)
                             : launch_generic<OpMax, 16, 2>(x, n, w, y, count, tw, s);
     case kOpAffine:
         if (big) return launch_generic<OpAffine, 32, 1>(x, n, w, y, count, tw, s);
@@ -912,8 +942,9 @@ int launch_sliding_prefix(int op, const void* x, uint64_t n, uint32_t w, void* y
                            static_cast<uint32_t*>(y), count, ntiles, vec);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
-    return w > (uint32_t)(kWave * 16) ? launch_generic<OpAdd, 32, 1, true>(x, n, w, y, count, tw, s)
-                                      : launch_generic<OpAdd, 16, 2, true>(x, n, w, y, count, tw, s);
+    if (w > (uint32_t)(kWave * 16)) return launch_generic<OpAdd, 32, 1, true>(x, n, w, y, count, tw, s);
+    if (w >= kEarlyHaloMinW) return launch_generic<OpAdd, 16, 2, true, true>(x, n, w, y, count, tw, s);
+    return launch_generic<OpAdd, 16, 2, true>(x, n, w, y, count, tw, s);
 }
 
 // ---------------------------------------------------------------------------
