@@ -43,8 +43,9 @@ extern "C" {
  * 3: sws_minimizers_batch_ex takes the workgroup size per call; the process-wide
  *    sws_set_minimizer_block is gone; sws_set_sliding_waves is per thread.
  * 4: sws_sliding_sum_workspace / sws_sliding_sum_ws (windows of any length) and
- *    sws_minimizers_noalloc (additions; no call changed its meaning). */
-#define SWS_ABI_VERSION 4u
+ *    sws_minimizers_noalloc (additions; no call changed its meaning).
+ * 5: the batched calls accept SWS_WORKSPACE_KEPT (an addition). */
+#define SWS_ABI_VERSION 5u
 
 typedef enum {
     SWS_OK = 0,
@@ -92,7 +93,8 @@ enum {
                                   segments and a window holding an invalid k-mer stores
                                   nothing (each segment as its own sequence, positions
                                   kept); w <= 32, else SWS_ERR_UNSUPPORTED            */
-    SWS_WORKSPACE_KEPT = 8u    /* sws_minimizers / sws_minimizers_2bit only: the workspace
+    SWS_WORKSPACE_KEPT = 8u    /* sws_minimizers / sws_minimizers_2bit and the batched
+                                  calls (sws_minimizers_batch / _ex) only: the workspace
                                   holds what the previous call with this flag left, or
                                   was zero-filled, and nothing else wrote it since; the
                                   call then skips clearing it (one kernel launch fewer).
@@ -295,6 +297,12 @@ int sws_minimizers_batch_workspace(uint64_t total_bases, uint32_t nreads, uint32
  * write an entry at or past capacity, and off[nreads] reports the full total,
  * so a total above capacity means the outputs were truncated.
  * total_bases must be < 2^32 - 1 (SWS_ERR_UNSUPPORTED otherwise).
+ * flags: SWS_KMER_* | SWS_HASH_* | SWS_SPLIT_AT_INVALID | SWS_WORKSPACE_KEPT.
+ * workspace: ws_bytes bytes of device scratch, 8-byte aligned, at least
+ * sws_minimizers_batch_workspace(total_bases, nreads, k, w); its contents on
+ * entry do not matter (the call clears what it uses), unless flags holds
+ * SWS_WORKSPACE_KEPT (see there); the call leaves it valid for a later
+ * batched call with that flag, of any size it is large enough for.
  */
 int sws_minimizers_batch(const uint8_t *seqs, const uint64_t *d_offsets, uint32_t nreads,
                          uint64_t total_bases, uint32_t k, uint32_t w, uint32_t flags,

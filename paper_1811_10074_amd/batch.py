@@ -90,7 +90,10 @@ class BatchRunner:
         self.read = torch.empty(cap, dtype=torch.int32, device=device)
         self.read_out = torch.zeros(self.nreads + 1, dtype=torch.int64, device=device)
         ws = batch_workspace_bytes(self.total, self.nreads, k, w)
-        self.workspace = torch.empty(max(ws, 8), dtype=torch.uint8, device=device)
+        # zero-filled once, then kept by the library between calls
+        # (SWS_WORKSPACE_KEPT), which saves clearing it on every call
+        self.workspace = torch.zeros(max(ws, 8), dtype=torch.uint8, device=device)
+        self.calls = 0
         for name in ("offsets", "hash", "pos", "read", "read_out", "workspace"):
             _need_cuda(getattr(self, name), name)
 
@@ -98,9 +101,14 @@ class BatchRunner:
         """Enqueue on the current stream; threads overrides the runner's
         workgroup size for this call."""
         t = self.threads if threads is None else int(threads)
+        fl = self.flags
+        # the library asks for a call without the flag at least every 2^30 calls
+        if self.calls % (1 << 29) != 0:
+            fl |= _lib.WORKSPACE_KEPT
+        self.calls += 1
         st = _lib.load().sws_minimizers_batch_ex(
             _ptr(self.seqs), _ptr(self.offsets), self.nreads, self.total, self.k, self.w,
-            self.flags, _ptr(self.hash), _ptr(self.pos), _ptr(self.read), self.capacity,
+            fl, _ptr(self.hash), _ptr(self.pos), _ptr(self.read), self.capacity,
             _ptr(self.read_out), _ptr(self.workspace), self.workspace.numel(), t, _stream())
         check(st, "sws_minimizers_batch_ex")
 
@@ -171,7 +179,9 @@ class BucketedBatch:
 
     def capture(self):
         """Record every bucket's launches into one HIP graph (block sizes are
-        fixed at capture time)."""
+        fixed at capture time).  The captured calls keep their workspaces
+        (SWS_WORKSPACE_KEPT, after the warm-up call), so the graph holds no
+        clearing kernel; capture again before 2^30 replays."""
         torch = _torch()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())

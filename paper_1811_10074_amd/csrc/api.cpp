@@ -304,7 +304,7 @@ int sws_minimizers_noalloc(const uint8_t* seq, uint64_t n, uint32_t k, uint32_t 
 // Batched calls need w <= 32 (one wavefront's tile) and k + w <= 49 (the
 // boundary bits a lane tests fit in 64).
 int check_batch_args(uint64_t total, uint32_t k, uint32_t w, uint32_t flags) {
-    if (k < 1 || k > 31 || w < 1 || !known_flags(flags)) return SWS_ERR_INVALID;
+    if (k < 1 || k > 31 || w < 1 || !known_flags(flags, true, true)) return SWS_ERR_INVALID;
     if (w > 32 || k + w > 49) return SWS_ERR_UNSUPPORTED;
     if (total >= kMaxPositions) return SWS_ERR_UNSUPPORTED;
     return SWS_OK;
@@ -359,7 +359,7 @@ int sws_minimizers_batch_ex(const uint8_t* seqs, const uint64_t* d_offsets, uint
     a.total = total_bases;
     a.k = k;
     a.w = w;
-    a.flags = flags;
+    a.flags = flags & ~(uint32_t)SWS_WORKSPACE_KEPT;  // the kernels see the k-mer flags only
     a.tw = sws::batch_tile_windows(k, w);
     a.ntiles = ntiles;
     a.out_hash = out_hash;
@@ -367,8 +367,10 @@ int sws_minimizers_batch_ex(const uint8_t* seqs, const uint64_t* d_offsets, uint
     a.out_read = out_read;
     a.capacity = capacity;
     a.read_out = d_read_out_offsets;
-    return sws::launch_minimizers_batch(in, a, threads, workspace, s) == 0 ? SWS_OK
-                                                                          : SWS_ERR_DEVICE;
+    return sws::launch_minimizers_batch(in, a, threads, workspace, s,
+                                        (flags & SWS_WORKSPACE_KEPT) != 0u) == 0
+               ? SWS_OK
+               : SWS_ERR_DEVICE;
 }
 
 int sws_minimizers_batch(const uint8_t* seqs, const uint64_t* d_offsets, uint32_t nreads,

@@ -1478,14 +1478,17 @@ static void launch_batch_variant(const GenomeInput& in, const BatchArgs& a, hipS
 }
 
 int launch_minimizers_batch(const GenomeInput& in, BatchArgs a, uint32_t nt, void* workspace,
-                            hipStream_t s) {
+                            hipStream_t s, bool kept) {
     uint8_t* ws = static_cast<uint8_t*>(workspace);
     a.err = reinterpret_cast<uint32_t*>(ws + 8);
     a.status = reinterpret_cast<uint64_t*>(ws + kWsStatusOffset);
     a.epoch = reinterpret_cast<uint64_t*>(ws + 16);
     a.first_read = reinterpret_cast<uint32_t*>(ws + kWsStatusOffset + 8 * kStatusStride * a.ntiles);
-    if (launch_zero(reinterpret_cast<uint64_t*>(ws), kWsStatusOffset / 8 + kStatusStride * a.ntiles,
-                    s) != 0)
+    // a kept workspace holds an earlier call's epoch and status words, which
+    // the epoch tells apart from this call's (as in launch_minimizers); the
+    // read table is rewritten below either way
+    if (!kept && launch_zero(reinterpret_cast<uint64_t*>(ws),
+                             kWsStatusOffset / 8 + kStatusStride * a.ntiles, s) != 0)
         return -1;
     const uint64_t rb = ((uint64_t)a.nreads + 255) / 256;
     hipLaunchKernelGGL(batch_first_read_kernel, dim3((unsigned)(rb < 4096 ? (rb ? rb : 1) : 4096)),

@@ -78,7 +78,7 @@ struct BatchArgs {
 
 int launch_zero(uint64_t* p, uint64_t words, hipStream_t s);
 int launch_minimizers_batch(const GenomeInput& in, BatchArgs a, uint32_t nt, void* workspace,
-                            hipStream_t s);
+                            hipStream_t s, bool kept);
 uint64_t batch_workspace_bytes(uint64_t ntiles);
 uint32_t batch_tile_windows(uint32_t k, uint32_t w);
 int launch_pack2bit(const uint8_t* seq, uint64_t n, uint32_t* packed, uint32_t* invalid,

@@ -25,7 +25,7 @@ def test_exports_every_header_function(lib):
 
 
 def test_version_and_status(lib):
-    assert lib.sws_abi_version() == 4
+    assert lib.sws_abi_version() == 5
     for st in (0, -1, -2, -3, -4, -5):
         assert lib.sws_status_str(st)
     assert b"unknown" in lib.sws_status_str(7)
@@ -93,11 +93,15 @@ def test_minimizer_validation(lib):
     assert lib.sws_kmers(FAKE, 1000, 15, 4, FAKE, s) == _lib.SWS_ERR_INVALID
     assert lib.sws_minimizers(FAKE, 1000, 15, 10, 16, FAKE, FAKE, 1 << 20, FAKE, FAKE, 1 << 30,
                               s) == _lib.SWS_ERR_INVALID
-    # a kept workspace is a single-sequence option: k-mers and batches refuse it
+    # a kept workspace is a minimizer option: k-mers refuse it; the batched
+    # call takes it (and then stops at the too-small workspace, before any
+    # launch), but not with an unknown bit beside it
     kept = _lib.WORKSPACE_KEPT
     assert lib.sws_kmers(FAKE, 1000, 15, kept, FAKE, s) == _lib.SWS_ERR_INVALID
     assert lib.sws_minimizers_batch(FAKE, FAKE, 10, 1000, 15, 10, kept, FAKE, FAKE, FAKE, 1 << 20,
-                                    FAKE, FAKE, 1 << 30, s) == _lib.SWS_ERR_INVALID
+                                    FAKE, FAKE, 8, s) == _lib.SWS_ERR_WORKSPACE
+    assert lib.sws_minimizers_batch(FAKE, FAKE, 10, 1000, 15, 10, kept | 16, FAKE, FAKE, FAKE,
+                                    1 << 20, FAKE, FAKE, 1 << 30, s) == _lib.SWS_ERR_INVALID
     # the prefix-difference path exists for + only
     for op in (1, 2, 3):
         assert lib.sws_sliding_sum_ex(op, 4, FAKE, 100, FAKE, 3, s) == _lib.SWS_ERR_UNSUPPORTED

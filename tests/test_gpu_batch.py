@@ -254,3 +254,45 @@ def test_config4_full_batch():
             assert np.array_equal(host_u64(h), xh), (rep, b)
     del bb
     torch.cuda.empty_cache()
+
+
+def test_kept_workspace_across_batches():
+    """SWS_WORKSPACE_KEPT on the batched call: one zero-filled workspace shared
+    by batches of falling and rising size (the look-back status words of
+    earlier calls stay in it, told apart by their epoch), with a call without
+    the flag in between and both look-back windows' workgroup sizes; every
+    call against the oracle, read by read."""
+    torch = torch_cuda()
+    import ctypes
+    from paper_1811_10074_amd import _lib
+    from paper_1811_10074_amd.batch import batch_workspace_bytes
+    lib = _lib.load()
+    k, w = 15, 10
+    rng = np.random.default_rng(77)
+    plan = [(400, 0), (40, _lib.WORKSPACE_KEPT), (3, _lib.WORKSPACE_KEPT), (400, _lib.WORKSPACE_KEPT),
+            (150, 0), (250, _lib.WORKSPACE_KEPT), (400, _lib.WORKSPACE_KEPT)]
+    batches = [make_batch(rng.integers(0, 2500, nr), seed=900 + i, n_rate=0.01)
+               for i, (nr, _) in enumerate(plan)]
+    ws_bytes = max(batch_workspace_bytes(int(o[-1]), o.size - 1, k, w) for _, o in batches)
+    ws = torch.zeros(ws_bytes, dtype=torch.uint8, device="cuda")
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    for i, ((seqs, off), (_, kept)) in enumerate(zip(batches, plan)):
+        eh, ep, er, ero = oracle.minimizers_batch(seqs, off, k, w)
+        cap = max(1, int(ero[-1]))
+        d_seq = torch.from_numpy(seqs).cuda()
+        d_off = torch.from_numpy(off.view(np.int64)).cuda()
+        h = torch.empty(cap, dtype=torch.int64, device="cuda")
+        p = torch.empty(cap, dtype=torch.int32, device="cuda")
+        r = torch.empty(cap, dtype=torch.int32, device="cuda")
+        ro = torch.empty(off.size, dtype=torch.int64, device="cuda")
+        threads = 256 if i % 2 == 0 else 128
+        st = lib.sws_minimizers_batch_ex(ptr(d_seq), ptr(d_off), off.size - 1, int(off[-1]), k, w,
+                                         kept, ptr(h), ptr(p), ptr(r), cap, ptr(ro), ptr(ws),
+                                         ws_bytes, threads, torch.cuda.current_stream().cuda_stream)
+        assert st == _lib.SWS_OK, (i, st)
+        torch.cuda.synchronize()
+        got_ro = ro.cpu().numpy().view(np.uint64)
+        assert np.array_equal(got_ro, ero), i
+        n = int(ero[-1])
+        assert np.array_equal(host_u64(h[:n]), eh) and np.array_equal(host_u32(p[:n]), ep), i
+        assert np.array_equal(host_u32(r[:n]), er), i
