@@ -846,10 +846,11 @@ int launch_sliding_scalar(int op, const void* x, uint64_t n, uint32_t w, void* y
 // ---------------------------------------------------------------------------
 constexpr uint64_t kDefaultSlidingWaves = 256ull * 128ull;  // 128 per compute unit
 // Windows from this length load their halo early (EARLY_HALO).  At n = 2^28,
-// w = 1024, timed per call: + (the prefix-difference form) 0.675 -> 0.74 of
-// HBM peak, min and max 0.67 -> 0.73; + at w = 768 0.69 -> 0.73.  Four waves
-// per workgroup (more neighbours sharing a CU) measured no better than two.
-constexpr uint32_t kEarlyHaloMinW = 512;
+// timed per call (fraction of HBM peak): w = 1024, + (the prefix-difference
+// form) 0.675 -> 0.74, min and max 0.67 -> 0.73; + at w = 768 0.69 -> 0.73;
+// w = 128 and 256 0.71 -> 0.72, max at w = 384 0.70 -> 0.71.  Four waves per
+// workgroup (more neighbours sharing a CU) measured no better than two.
+constexpr uint32_t kEarlyHaloMinW = 128;
 
 template <class Op, int R, int WAVES, bool PFX = false, bool EARLY_HALO = false>
 static int launch_generic(const void* x, uint64_t n, uint32_t w, void* y, uint64_t count,
