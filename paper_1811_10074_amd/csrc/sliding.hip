@@ -848,8 +848,10 @@ constexpr uint64_t kDefaultSlidingWaves = 256ull * 128ull;  // 128 per compute u
 // Windows from this length load their halo early (EARLY_HALO).  At n = 2^28,
 // timed per call (fraction of HBM peak): w = 1024, + (the prefix-difference
 // form) 0.675 -> 0.74, min and max 0.67 -> 0.73; + at w = 768 0.69 -> 0.73;
-// w = 128 and 256 0.71 -> 0.72, max at w = 384 0.70 -> 0.71.  Four waves per
-// workgroup (more neighbours sharing a CU) measured no better than two.
+// w = 128 and 256 0.71 -> 0.72, max at w = 384 0.70 -> 0.71; affine (8-pair
+// runs) at w = 128 and 256 0.71 -> 0.73.  Four waves per workgroup (more
+// neighbours sharing a CU) measured no better than two.  Affine above w = 512
+// (241 VGPRs at R = 16) has no room for the halo's registers.
 constexpr uint32_t kEarlyHaloMinW = 128;
 
 template <class Op, int R, int WAVES, bool PFX = false, bool EARLY_HALO = false>
@@ -924,7 +926,8 @@ int launch_sliding_generic(int op, const void* x, uint64_t n, uint32_t w, void* 
     case kOpAffine:
         if (big) return launch_generic<OpAffine, 32, 1>(x, n, w, y, count, tw, s);
         if (w > (uint32_t)(kWave * 8)) return launch_generic<OpAffine, 16, 1>(x, n, w, y, count, tw, s);
-        return launch_generic<OpAffine, 8, 2>(x, n, w, y, count, tw, s);
+        return early ? launch_generic<OpAffine, 8, 2, false, true>(x, n, w, y, count, tw, s)
+                     : launch_generic<OpAffine, 8, 2>(x, n, w, y, count, tw, s);
     default: return -2;
     }
 }
