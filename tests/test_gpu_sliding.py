@@ -227,11 +227,14 @@ def test_long_streams_per_wave(few_waves, waves, op):
     first slab, the last in-range steps of a wave and the checked steps at
     the end, with n on either side of the slab boundaries that decide between
     them; waves of one slab, of fewer slabs than are in flight, and of odd and
-    even slab counts (two register buffers alternate)."""
+    even slab counts (two register buffers alternate).  Windows from 128 on
+    load the next wave's first slab at the wave's start instead (w = 127 and
+    128 on either side of that, 512 the last such window of 8-element affine
+    runs)."""
     torch = torch_cuda()
     few_waves(waves)
     seed = {"add": 21, "min": 22, "max": 23, "affine": 24}[op]
-    for w in (1, 16, 17, 1024, 1025, 2048):
+    for w in (1, 16, 17, 127, 128, 512, 1024, 1025, 2048):
         S = _slab(op, w)
         for n in (2 * S + w, 3 * S - 1, 3 * S + w - 1, 4 * S + w, 5 * S + w - 2, 7 * S + w + 1,
                   12 * S + 3):
