@@ -314,14 +314,19 @@ __global__ __launch_bounds__(kSeedNT) void seed_scatter_kernel(
         const uint64_t i = b * kSeedTile + tile_slot(wv, r, lane);
         const bool valid = i < count;
         const uint32_t d = (item[r].key(shift, mask) >> dshift) & 0xFFu;
-        // lanes holding the same digit (valid lanes only)
-        uint64_t same = __ballot(valid);
+        // lanes holding the same digit (valid lanes only): a lane differs
+        // from this one where some bit of the two digits differs, i.e. where
+        // the bit's ballot differs from this lane's bit spread to a word
+        // (0 or all ones; a signed 1-bit field extract), per 32-lane half
+        uint32_t diff_lo = 0u, diff_hi = 0u;
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
-            const bool on = (d >> bit) & 1u;
-            const uint64_t bal = __ballot(on);
-            same &= on ? bal : ~bal;
+            const uint32_t spread = (uint32_t)(((int32_t)(d << (31 - bit))) >> 31);
+            const uint64_t bal = __ballot(spread != 0u);
+            diff_lo |= (uint32_t)bal ^ spread;
+            diff_hi |= (uint32_t)(bal >> 32) ^ spread;
         }
+        const uint64_t same = ~(((uint64_t)diff_hi << 32) | diff_lo) & __ballot(valid);
         const uint32_t prior = valid ? cnt[wv][d] : 0u;
         rank[r] = prior + (uint32_t)__builtin_popcountll(same & below);
         // the highest lane of each group advances the group's count
